@@ -1,0 +1,174 @@
+/*
+ * sdugks.h -- C ABI of the MI355X (gfx950) sDUGKS solver library, libsdugks.so.
+ *
+ * The library advances the D2Q9 BGK distribution of a 2-D finite-volume mesh
+ * with the simplified discrete unified gas kinetic scheme of Zhong et al.,
+ * "A simplified discrete unified gas kinetic scheme for incompressible flow"
+ * (arXiv:2007.07347).  The problem it solves is the one stated in Section II:
+ * given control volumes V_j, boundary conditions (Section III), a relaxation
+ * time (or viscosity) and a time step, march f, rho and u from t_n to t_{n+1}
+ * by the eleven-step summary at the end of Section II, until the velocity
+ * residual of the lid-driven cavity case (Section IV) falls below a tolerance.
+ *
+ * Conventions for every call:
+ *  - Return value: 0 (SDUGKS_OK) or a negative SDUGKS_E* code.  Nothing throws
+ *    across the ABI.  sdugks_last_error() returns a thread-local message for
+ *    the last failing call of the calling thread.
+ *  - Ownership: inputs are copied; the caller may free them when the call
+ *    returns.  A handle owns the device memory it allocates; with a caller
+ *    workspace, the caller owns that memory and must keep it alive and
+ *    untouched until sdugks_destroy.
+ *  - Cell order: every per-cell array crossing the ABI is in the caller's cell
+ *    order (the order of mesh.cell_ptr), whatever internal reordering is used.
+ *  - Layout: per-cell arrays are row-major, cell-major: f[n_cells][9] in the
+ *    D2Q9 order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1),
+ *    W[n_cells][3] = (rho, rho*u, rho*v).  All host pointers unless stated.
+ *  - Streams: device work is enqueued on the hipStream_t given at creation
+ *    (NULL = the null stream).  sdugks_step is asynchronous; calls that return
+ *    host data synchronise that stream first.
+ *  - Threads: one handle must not be used by two threads at once.
+ */
+#ifndef SDUGKS_H
+#define SDUGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SDUGKS_OK = 0,
+    SDUGKS_EINVAL = -1,     /* bad argument or invalid mesh */
+    SDUGKS_ENOMEM = -2,     /* host or device allocation failed, or workspace too small */
+    SDUGKS_EHIP = -3,       /* a HIP runtime call failed (message names it) */
+    SDUGKS_EDIVERGED = -4,  /* a non-finite density or velocity was found; the handle refuses to step */
+    SDUGKS_ENODEV = -5      /* no gfx950 device usable */
+};
+
+/* Boundary-condition types, Section III.  WALL: rho from the adjacent cell,
+ * u = wall velocity.  INLET: (rho_inf, u_inf).  OUTLET: rho and u of the
+ * adjacent cell.  All three build the boundary distribution by
+ * non-equilibrium extrapolation, f_b = feq(rho_b, u_b) + (f_in - feq_in), and
+ * use it for the velocities with e_i . N < 0 (N outward).  PERIODIC: the tag's
+ * edges are glued to the partner tag's edges shifted by (shift_x, shift_y). */
+enum { SDUGKS_BC_WALL = 1, SDUGKS_BC_INLET = 2, SDUGKS_BC_OUTLET = 3, SDUGKS_BC_PERIODIC = 4 };
+
+/* Storage precision of f: FP64, or FP32 holding the deviation f - w_i rho0
+ * (density, momentum, mass and residual stay FP64). */
+enum { SDUGKS_FP64 = 0, SDUGKS_FP32DEV = 1 };
+
+/* Time level of the macroscopic flux of Eq. (MacroFlux) used by
+ * Eq. (MacroUpdate): this step's face fluxes (CURRENT, default) or the previous
+ * step's (LAGGED; stable only for dt below about 3 tau). */
+enum { SDUGKS_MACRO_LAGGED = 0, SDUGKS_MACRO_CURRENT = 1 };
+
+/* Raw mesh: polygons of 3..8 nodes, counter-clockwise.  Every edge of a cell
+ * that no other cell shares must appear once in bedge_nodes (either order). */
+typedef struct {
+    int32_t n_nodes;
+    const double *node_xy;        /* [n_nodes][2] */
+    int32_t n_cells;
+    const int32_t *cell_ptr;      /* [n_cells + 1] offsets into cell_nodes */
+    const int32_t *cell_nodes;    /* [cell_ptr[n_cells]] node ids */
+    int32_t n_bedges;
+    const int32_t *bedge_nodes;   /* [n_bedges][2] */
+    const int32_t *bedge_tag;     /* [n_bedges] index into the sdugks_bc table */
+} sdugks_mesh;
+
+typedef struct {
+    int32_t type;                 /* SDUGKS_BC_* */
+    int32_t partner;              /* PERIODIC: tag of the partner side */
+    double rho, u, v;             /* INLET: rho_inf, u_inf; WALL: u, v = wall velocity */
+    double shift_x, shift_y;      /* PERIODIC: this side + shift = partner side */
+} sdugks_bc;
+
+typedef struct {
+    double nu;                    /* kinematic viscosity; tau = nu / c_s^2 = 3 nu */
+    double tau;                   /* relaxation time; > 0 overrides nu */
+    double cfl;                   /* dt = cfl * h_min / sqrt(2) (h_j = 2 * min centroid-to-face distance) */
+    double dt;                    /* > 0 overrides cfl */
+    double rho0, u0, v0;          /* initial uniform equilibrium; rho0 is also the FP32DEV offset */
+    int32_t precision;            /* SDUGKS_FP64 or SDUGKS_FP32DEV */
+    int32_t macro_flux;           /* SDUGKS_MACRO_CURRENT (default) or SDUGKS_MACRO_LAGGED */
+    int32_t reorder;              /* 1 = reverse Cuthill-McKee cell order inside the library */
+    int32_t residual_interval;    /* steps between residual checks in serving loops (paper: 1000) */
+} sdugks_params;
+
+typedef struct sdugks_s sdugks_t;
+
+/* Host-only mesh build, no device needed.  Outputs may be NULL.  dt, tau: the
+ * values sdugks_create would use; h_min: min_j h_j; n_faces: faces after
+ * periodic gluing; area, cx, cy: [n_cells] cell area and centroid in the
+ * caller's order; perm: [n_cells], perm[k] = caller index of the k-th cell in
+ * the library's internal order. */
+int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                    double *dt, double *tau, double *h_min, int32_t *n_faces,
+                    double *area, double *cx, double *cy, int32_t *perm);
+
+/* Device bytes a handle for this problem needs (all state, geometry and
+ * scratch); the size of a caller workspace.  Host only. */
+int sdugks_state_bytes(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                       size_t *bytes);
+
+/* Build the mesh, upload it, and set f = feq(rho0, u0, v0), W = (rho0, rho0 u0,
+ * rho0 v0), G = 0 on the current HIP device.  stream: a hipStream_t or NULL.
+ * workspace: device memory of at least sdugks_state_bytes bytes, 256-byte
+ * aligned, or NULL for the library to allocate. */
+int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                  void *stream, void *workspace, size_t workspace_bytes, sdugks_t **out);
+
+/* Advance n >= 0 time steps (asynchronous).  Fails with SDUGKS_EDIVERGED once a
+ * residual, mass or state call has seen a non-finite value. */
+int sdugks_step(sdugks_t *h, int64_t n);
+
+/* rho, u, v: [n_cells] host arrays (any may be NULL).  Synchronises. */
+int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v);
+
+/* Full state: f [n_cells][9], W [n_cells][3], G [n_cells][3] (the stored
+ * macroscopic flux of the lagged mode; zeros otherwise).  Any may be NULL.
+ * With FP32DEV storage f is returned as w_i rho0 + (stored deviation). */
+int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G);
+int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double *G);
+
+/* eps = sqrt(sum_j |u_j - u_j^snap|^2) / sqrt(sum_j |u_j^snap|^2) over cells
+ * (unweighted), the residual of the paper's cavity case, against the snapshot
+ * taken by the previous call (or at create / set_state), then re-snapshots.
+ * +inf when the snapshot is all zero.  Deterministic FP64 reduction.
+ * Returns SDUGKS_EDIVERGED if any rho or u is not finite.  Synchronises. */
+int sdugks_residual(sdugks_t *h, double *eps);
+
+/* mass = sum_j V_j rho_j, deterministic FP64 reduction.  Synchronises. */
+int sdugks_mass(sdugks_t *h, double *mass);
+
+/* Any output may be NULL. */
+int sdugks_info(sdugks_t *h, double *dt, double *tau, int64_t *step, int32_t *n_cells);
+
+/* Average device duration (milliseconds) of each kernel of the step over the
+ * next n steps, measured with HIP events on the handle's stream around every
+ * launch (slower than sdugks_step; for profiling).  names: optional array of
+ * max_kernels const char* receiving static kernel names.  *n_kernels: count. */
+int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **names, int32_t max_kernels,
+                         int32_t *n_kernels);
+
+int sdugks_destroy(sdugks_t *h);
+
+const char *sdugks_last_error(void);
+
+/* ---- batched form: many independent instances advanced by one launch per step.
+ * Members keep their own state and must share precision and macro mode; they
+ * stay usable individually.  The batch does not own them. */
+typedef struct sdugks_batch_s sdugks_batch_t;
+int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugks_batch_t **out);
+int sdugks_batch_step(sdugks_batch_t *b, int64_t n);
+int sdugks_batch_destroy(sdugks_batch_t *b);
+
+/* Failure injection for tests: writes NaN into f of one cell and velocity
+ * (caller cell order). */
+int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

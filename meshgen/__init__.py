@@ -260,3 +260,36 @@ def random_state(n_cells, seed, amp=0.05, rho0=1.0):
 
 def log_uniform_int(rng, lo, hi, size=None):
     return np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=size))).astype(np.int64)
+
+
+def hexagon_strip(nx, ny, lx=1.0, ly=1.0, lid_u=0.1):
+    """Structured box whose vertical edges carry a midpoint node, so every
+    cell is a hexagon with two collinear faces on each side (six faces per
+    cell).  Tags: 0 = resting walls, 1 = lid y = ly moving at (lid_u, 0)."""
+    xs = np.linspace(0.0, lx, nx + 1)
+    ys = np.linspace(0.0, ly, 2 * ny + 1)          # every other row is a midpoint row
+    X, Y = np.meshgrid(xs, ys)
+    node_xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    nid = lambda i, j: j * (nx + 1) + i  # noqa: E731
+    cells = []
+    for j in range(ny):
+        for i in range(nx):
+            b, m, t = 2 * j, 2 * j + 1, 2 * j + 2
+            cells.append([nid(i, b), nid(i + 1, b), nid(i + 1, m), nid(i + 1, t), nid(i, t), nid(i, m)])
+    bedges, tags = [], []
+    for i in range(nx):
+        bedges.append((nid(i, 0), nid(i + 1, 0))); tags.append(0)
+        bedges.append((nid(i, 2 * ny), nid(i + 1, 2 * ny))); tags.append(1)
+    for j in range(2 * ny):
+        bedges.append((nid(0, j), nid(0, j + 1))); tags.append(0)
+        bedges.append((nid(nx, j), nid(nx, j + 1))); tags.append(0)
+    return _pack(node_xy, cells, bedges, tags), [bc(WALL), bc(WALL, u=lid_u)]
+
+
+def inlet_outlet_box(nx, ny, u_in=0.05):
+    """Channel on [0,1]^2: inlet (rho 1, u_in) on the left, outlet on the right,
+    walls at rest below and above (all four boundary types but periodic)."""
+    xs = np.linspace(0.0, 1.0, nx + 1)
+    ys = tanh_nodes(ny, 1.0)
+    mesh = structured(xs, ys, tag_bottom=0, tag_right=1, tag_top=0, tag_left=2)
+    return mesh, [bc(WALL), bc(OUTLET), bc(INLET, rho=1.0, u=u_in, v=0.0)]

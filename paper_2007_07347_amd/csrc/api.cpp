@@ -1,0 +1,528 @@
+// C ABI of libsdugks.so: handles, device memory, step driver, reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sdugks.h"
+#include "device.h"
+#include "mesh.h"
+
+using namespace sdg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail(SDUGKS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Byte layout of one handle's device memory.  Everything is carved from one
+// block: per-cell rows are pitched to np = nc rounded up to 64.
+struct Layout {
+    size_t np = 0;
+    size_t off_f[2]{}, off_W[2]{}, off_G[2]{}, off_fbp = 0, off_sg = 0, off_snap = 0;
+    size_t off_nbr = 0, off_geo = 0, off_ainv = 0, off_dtv = 0, off_area = 0, off_bft = 0, off_bcs = 0;
+    size_t off_part = 0, off_out = 0, total = 0;
+};
+
+Layout make_layout(const MeshBuild &mb)
+{
+    Layout L;
+    L.np = ((size_t)mb.nc + 63) / 64 * 64;
+    const size_t row = L.np * sizeof(double);
+    size_t p = 0;
+    auto take = [&](size_t bytes) { size_t o = p; p += align_up(bytes); return o; };
+    for (int k = 0; k < 2; k++) {
+        L.off_f[k] = take(9 * row);
+        L.off_W[k] = take(3 * row);
+        L.off_G[k] = take(3 * row);
+    }
+    L.off_fbp = take(9 * row);
+    L.off_sg = take(18 * row);
+    L.off_snap = take(2 * row);
+    L.off_nbr = take((size_t)mb.D * L.np * sizeof(int32_t));
+    L.off_geo = take(6 * (size_t)mb.D * row);
+    L.off_ainv = take(3 * row);
+    L.off_dtv = take(row);
+    L.off_area = take(row);
+    L.off_bft = take(std::max<size_t>(1, mb.n_bfaces) * sizeof(int32_t));
+    L.off_bcs = take(std::max<size_t>(1, mb.bcs.size()) * sizeof(DevBC));
+    L.off_part = take(4 * kReduceBlocks * sizeof(double));
+    L.off_out = take(4 * sizeof(double));
+    L.total = p;
+    return L;
+}
+
+}  // namespace
+
+struct sdugks_s {
+    MeshBuild mb;
+    Layout L;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    char *base = nullptr;
+    bool own = false;
+    int cur = 0;                 // index of the current (input) state buffers
+    int64_t step = 0;
+    bool diverged = false;
+    int precision = SDUGKS_FP64, macro = SDUGKS_MACRO_CURRENT;
+    double rho0 = 1.0;
+    DevMesh dm{};
+    double *host4 = nullptr;     // pinned, 4 doubles
+
+    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
+    DevState state() const
+    {
+        DevState s;
+        s.f = at<double>(L.off_f[cur]); s.W = at<double>(L.off_W[cur]); s.G = at<double>(L.off_G[cur]);
+        s.fo = at<double>(L.off_f[cur ^ 1]); s.Wo = at<double>(L.off_W[cur ^ 1]); s.Go = at<double>(L.off_G[cur ^ 1]);
+        return s;
+    }
+    DevScratch scratch() const { return {at<double>(L.off_fbp), at<double>(L.off_sg)}; }
+};
+
+struct sdugks_batch_s {
+    std::vector<sdugks_t *> members;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+int check_prm(const sdugks_params *prm)
+{
+    if (!prm) return fail(SDUGKS_EINVAL, "null params");
+    if (prm->precision != SDUGKS_FP64) return fail(SDUGKS_EINVAL, "precision: only SDUGKS_FP64 is built in this library");
+    if (prm->macro_flux != SDUGKS_MACRO_CURRENT && prm->macro_flux != SDUGKS_MACRO_LAGGED)
+        return fail(SDUGKS_EINVAL, "macro_flux must be SDUGKS_MACRO_CURRENT or SDUGKS_MACRO_LAGGED");
+    if (!(prm->rho0 > 0)) return fail(SDUGKS_EINVAL, "rho0 must be positive");
+    return SDUGKS_OK;
+}
+
+int build(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm, MeshBuild &mb)
+{
+    int rc = check_prm(prm);
+    if (rc) return rc;
+    std::string err;
+    rc = build_mesh(mesh, bc, n_bc, prm, mb, err);
+    if (rc) return fail(rc, "mesh: " + err);
+    return SDUGKS_OK;
+}
+
+// Upload helper: host vector into a pitched [rows][np] device block.
+template <typename T>
+int upload_rows(T *dst, const std::vector<T> &src, size_t rows, size_t nc, size_t np, hipStream_t st)
+{
+    std::vector<T> tmp(rows * np, T(0));
+    for (size_t r = 0; r < rows; r++) std::copy(src.begin() + r * nc, src.begin() + (r + 1) * nc, tmp.begin() + r * np);
+    HIPCHK(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return SDUGKS_OK;
+}
+
+double feq_host(int i, double rho, double ux, double uy)
+{
+    static const double ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1}, ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    const double eu = ex[i] * ux + ey[i] * uy, uu = ux * ux + uy * uy;
+    return w[i] * rho * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+int sync_check(sdugks_t *h)
+{
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SDUGKS_OK;
+}
+
+// Run the reduction kernel and fetch {num, den, mass, nonfinite}.
+int reduce(sdugks_t *h, int update_snap, double out[4])
+{
+    HIPCHK(hipSetDevice(h->device));
+    DevState s = h->state();
+    HIPCHK(launch_reduce(h->dm, s.W, h->at<double>(h->L.off_snap), update_snap, h->at<double>(h->L.off_part),
+                         h->at<double>(h->L.off_out), h->stream));
+    HIPCHK(hipMemcpyAsync(h->host4, h->at<double>(h->L.off_out), 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    std::memcpy(out, h->host4, 4 * sizeof(double));
+    if (out[3] != 0.0) h->diverged = true;
+    return SDUGKS_OK;
+}
+
+int enqueue_step(sdugks_t *h)
+{
+    DevState s = h->state();
+    DevScratch x = h->scratch();
+    HIPCHK(launch_grad(h->dm, s, x, h->stream));
+    HIPCHK(launch_flux_update(h->dm, s, x, h->macro == SDUGKS_MACRO_LAGGED, h->stream));
+    h->cur ^= 1;
+    h->step++;
+    return SDUGKS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sdugks_last_error(void) { return g_err.c_str(); }
+
+int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                    double *dt, double *tau, double *h_min, int32_t *n_faces, double *area, double *cx, double *cy,
+                    int32_t *perm)
+{
+    MeshBuild mb;
+    int rc = build(mesh, bc, n_bc, prm, mb);
+    if (rc) return rc;
+    if (dt) *dt = mb.dt;
+    if (tau) *tau = mb.tau;
+    if (h_min) *h_min = mb.h_min;
+    if (n_faces) *n_faces = mb.n_faces;
+    for (int32_t k = 0; k < mb.nc; k++) {
+        int32_t c = mb.perm[k];
+        if (area) area[c] = mb.area[k];
+        if (cx) cx[c] = mb.cx[k];
+        if (cy) cy[c] = mb.cy[k];
+        if (perm) perm[k] = c;
+    }
+    return SDUGKS_OK;
+}
+
+int sdugks_state_bytes(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                       size_t *bytes)
+{
+    if (!bytes) return fail(SDUGKS_EINVAL, "null bytes");
+    MeshBuild mb;
+    int rc = build(mesh, bc, n_bc, prm, mb);
+    if (rc) return rc;
+    *bytes = make_layout(mb).total;
+    return SDUGKS_OK;
+}
+
+int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                  void *stream, void *workspace, size_t workspace_bytes, sdugks_t **out)
+{
+    if (!out) return fail(SDUGKS_EINVAL, "null out");
+    *out = nullptr;
+    sdugks_t *h = new (std::nothrow) sdugks_t();
+    if (!h) return fail(SDUGKS_ENOMEM, "host allocation failed");
+    int rc = build(mesh, bc, n_bc, prm, h->mb);
+    if (rc) { delete h; return rc; }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { delete h; return fail(SDUGKS_ENODEV, "no HIP device"); }
+    hipGetDevice(&h->device);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, h->device) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        delete h;
+        return fail(SDUGKS_ENODEV, "the current device is not gfx950");
+    }
+    h->stream = (hipStream_t)stream;
+    h->precision = prm->precision;
+    h->macro = prm->macro_flux;
+    h->rho0 = prm->rho0;
+    h->L = make_layout(h->mb);
+    const Layout &L = h->L;
+    if (workspace) {
+        if (workspace_bytes < L.total || ((uintptr_t)workspace % kAlign)) {
+            delete h;
+            return fail(SDUGKS_ENOMEM, "workspace smaller than sdugks_state_bytes or not 256-byte aligned");
+        }
+        h->base = (char *)workspace;
+    } else {
+        if (hipMalloc((void **)&h->base, L.total) != hipSuccess) { delete h; return fail(SDUGKS_ENOMEM, "hipMalloc of the state failed"); }
+        h->own = true;
+    }
+    if (hipHostMalloc((void **)&h->host4, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        if (h->own) hipFree(h->base);
+        delete h;
+        return fail(SDUGKS_ENOMEM, "pinned host allocation failed");
+    }
+    const MeshBuild &mb = h->mb;
+    const size_t nc = mb.nc, np = L.np;
+    auto cleanup = [&](int code) {
+        if (h->own) hipFree(h->base);
+        hipHostFree(h->host4);
+        delete h;
+        return code;
+    };
+    // geometry
+    rc = upload_rows(h->at<int32_t>(L.off_nbr), mb.nbr, mb.D, nc, np, h->stream);
+    if (rc) return cleanup(rc);
+    {
+        std::vector<double> geo((size_t)6 * mb.D * nc);
+        const std::vector<double> *parts[6] = {&mb.lnx, &mb.lny, &mb.rsx, &mb.rsy, &mb.rox, &mb.roy};
+        for (int k = 0; k < 6; k++) std::copy(parts[k]->begin(), parts[k]->end(), geo.begin() + (size_t)k * mb.D * nc);
+        rc = upload_rows(h->at<double>(L.off_geo), geo, 6 * (size_t)mb.D, nc, np, h->stream);
+        if (rc) return cleanup(rc);
+    }
+    rc = upload_rows(h->at<double>(L.off_ainv), mb.ainv, 3, nc, np, h->stream);
+    if (rc) return cleanup(rc);
+    {
+        std::vector<double> dtv(nc);
+        for (size_t c = 0; c < nc; c++) dtv[c] = mb.dt / mb.area[c];
+        rc = upload_rows(h->at<double>(L.off_dtv), dtv, 1, nc, np, h->stream);
+        if (rc) return cleanup(rc);
+        rc = upload_rows(h->at<double>(L.off_area), mb.area, 1, nc, np, h->stream);
+        if (rc) return cleanup(rc);
+    }
+    if (mb.n_bfaces) {
+        if (hipMemcpy(h->at<int32_t>(L.off_bft), mb.bf_tag.data(), mb.n_bfaces * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(SDUGKS_EHIP, "upload of boundary tags failed"));
+    }
+    {
+        std::vector<DevBC> bcs(mb.bcs.size());
+        for (size_t t = 0; t < bcs.size(); t++) bcs[t] = {mb.bcs[t].type, mb.bcs[t].rho, mb.bcs[t].u, mb.bcs[t].v};
+        if (!bcs.empty() && hipMemcpy(h->at<DevBC>(L.off_bcs), bcs.data(), bcs.size() * sizeof(DevBC), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(SDUGKS_EHIP, "upload of the boundary table failed"));
+    }
+    DevMesh &d = h->dm;
+    d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces;
+    d.nbr = h->at<int32_t>(L.off_nbr);
+    const double *geo = h->at<double>(L.off_geo);
+    const size_t blk = (size_t)mb.D * np;
+    d.lnx = geo; d.lny = geo + blk; d.rsx = geo + 2 * blk; d.rsy = geo + 3 * blk; d.rox = geo + 4 * blk; d.roy = geo + 5 * blk;
+    d.ainv = h->at<double>(L.off_ainv);
+    d.dtv = h->at<double>(L.off_dtv);
+    d.area = h->at<double>(L.off_area);
+    d.bf_tag = h->at<int32_t>(L.off_bft);
+    d.bcs = h->at<DevBC>(L.off_bcs);
+    const double tau = mb.tau, dt = mb.dt;
+    d.a = (2.0 * tau - dt) / (2.0 * tau);
+    d.b = dt / (2.0 * tau);
+    d.c1 = 2.0 * tau / (2.0 * tau + dt);
+    d.lam = dt / tau;
+    d.dt = dt;
+    // initial state: uniform equilibrium, G = 0, snapshot = initial velocity
+    {
+        std::vector<double> f(9 * nc), W(3 * nc), G(3 * nc, 0.0);
+        for (size_t c = 0; c < nc; c++) {
+            for (int i = 0; i < 9; i++) f[c * 9 + i] = feq_host(i, prm->rho0, prm->u0, prm->v0);
+            W[3 * c] = prm->rho0; W[3 * c + 1] = prm->rho0 * prm->u0; W[3 * c + 2] = prm->rho0 * prm->v0;
+        }
+        *out = h;
+        // set_state expects caller order; the uniform state is order-free
+        rc = sdugks_set_state(h, f.data(), W.data(), G.data());
+        if (rc) { *out = nullptr; return cleanup(rc); }
+    }
+    return SDUGKS_OK;
+}
+
+int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double *G)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(h->device));
+    const size_t nc = h->mb.nc, np = h->L.np;
+    const Layout &L = h->L;
+    std::vector<double> buf(9 * np, 0.0);
+    auto put = [&](const double *src, int rows, size_t off) -> int {
+        std::fill(buf.begin(), buf.end(), 0.0);
+        for (size_t k = 0; k < nc; k++) {
+            size_t c = h->mb.perm[k];
+            for (int r = 0; r < rows; r++) buf[r * np + k] = src[c * rows + r];
+        }
+        HIPCHK(hipMemcpyAsync(h->base + off, buf.data(), rows * np * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return SDUGKS_OK;
+    };
+    int rc;
+    if (f && (rc = put(f, 9, L.off_f[h->cur]))) return rc;
+    if (W) {
+        if ((rc = put(W, 3, L.off_W[h->cur]))) return rc;
+        // snapshot of the residual = this velocity field
+        std::vector<double> snap(2 * np, 0.0);
+        for (size_t k = 0; k < nc; k++) {
+            size_t c = h->mb.perm[k];
+            snap[k] = W[3 * c + 1] / W[3 * c];
+            snap[np + k] = W[3 * c + 2] / W[3 * c];
+        }
+        HIPCHK(hipMemcpyAsync(h->base + L.off_snap, snap.data(), 2 * np * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    }
+    if (G && (rc = put(G, 3, L.off_G[h->cur]))) return rc;
+    h->diverged = false;
+    return SDUGKS_OK;
+}
+
+int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    const size_t nc = h->mb.nc, np = h->L.np;
+    const Layout &L = h->L;
+    std::vector<double> buf(9 * np);
+    auto get = [&](double *dst, int rows, size_t off) -> int {
+        HIPCHK(hipMemcpyAsync(buf.data(), h->base + off, rows * np * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (size_t k = 0; k < nc; k++) {
+            size_t c = h->mb.perm[k];
+            for (int r = 0; r < rows; r++) dst[c * rows + r] = buf[r * np + k];
+        }
+        return SDUGKS_OK;
+    };
+    int rc;
+    if (f && (rc = get(f, 9, L.off_f[h->cur]))) return rc;
+    if (W && (rc = get(W, 3, L.off_W[h->cur]))) return rc;
+    if (G) {
+        if (h->macro == SDUGKS_MACRO_LAGGED) { if ((rc = get(G, 3, L.off_G[h->cur]))) return rc; }
+        else std::fill(G, G + 3 * nc, 0.0);
+    }
+    return SDUGKS_OK;
+}
+
+int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    std::vector<double> W(3 * (size_t)h->mb.nc);
+    int rc = sdugks_get_state(h, nullptr, W.data(), nullptr);
+    if (rc) return rc;
+    for (int32_t c = 0; c < h->mb.nc; c++) {
+        if (rho) rho[c] = W[3 * c];
+        if (u) u[c] = W[3 * c + 1] / W[3 * c];
+        if (v) v[c] = W[3 * c + 2] / W[3 * c];
+    }
+    return SDUGKS_OK;
+}
+
+int sdugks_step(sdugks_t *h, int64_t n)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    if (n < 0) return fail(SDUGKS_EINVAL, "negative step count");
+    if (h->diverged) return fail(SDUGKS_EDIVERGED, "state is not finite; reset it with sdugks_set_state");
+    HIPCHK(hipSetDevice(h->device));
+    for (int64_t k = 0; k < n; k++) {
+        int rc = enqueue_step(h);
+        if (rc) return rc;
+    }
+    return SDUGKS_OK;
+}
+
+int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **names, int32_t max_kernels,
+                         int32_t *n_kernels)
+{
+    if (!h || !avg_ms || max_kernels < 2 || !n_kernels) return fail(SDUGKS_EINVAL, "bad arguments");
+    if (h->diverged) return fail(SDUGKS_EDIVERGED, "state is not finite");
+    HIPCHK(hipSetDevice(h->device));
+    hipEvent_t ev[3];
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    double acc[2] = {0, 0};
+    for (int64_t k = 0; k < n; k++) {
+        DevState s = h->state();
+        DevScratch x = h->scratch();
+        HIPCHK(hipEventRecord(ev[0], h->stream));
+        HIPCHK(launch_grad(h->dm, s, x, h->stream));
+        HIPCHK(hipEventRecord(ev[1], h->stream));
+        HIPCHK(launch_flux_update(h->dm, s, x, h->macro == SDUGKS_MACRO_LAGGED, h->stream));
+        HIPCHK(hipEventRecord(ev[2], h->stream));
+        HIPCHK(hipEventSynchronize(ev[2]));
+        float a = 0, b = 0;
+        HIPCHK(hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIPCHK(hipEventElapsedTime(&b, ev[1], ev[2]));
+        acc[0] += a; acc[1] += b;
+        h->cur ^= 1;
+        h->step++;
+    }
+    for (auto &e : ev) hipEventDestroy(e);
+    avg_ms[0] = n ? acc[0] / n : 0;
+    avg_ms[1] = n ? acc[1] / n : 0;
+    if (names) { names[0] = "k_grad"; names[1] = "k_flux_update"; }
+    *n_kernels = 2;
+    return SDUGKS_OK;
+}
+
+int sdugks_residual(sdugks_t *h, double *eps)
+{
+    if (!h || !eps) return fail(SDUGKS_EINVAL, "null argument");
+    double r[4];
+    int rc = reduce(h, 1, r);
+    if (rc) return rc;
+    if (r[3] != 0.0) { *eps = NAN; return fail(SDUGKS_EDIVERGED, "non-finite density or velocity"); }
+    *eps = r[1] > 0 ? std::sqrt(r[0]) / std::sqrt(r[1]) : INFINITY;
+    return SDUGKS_OK;
+}
+
+int sdugks_mass(sdugks_t *h, double *mass)
+{
+    if (!h || !mass) return fail(SDUGKS_EINVAL, "null argument");
+    double r[4];
+    int rc = reduce(h, 0, r);
+    if (rc) return rc;
+    *mass = r[2];
+    if (r[3] != 0.0) return fail(SDUGKS_EDIVERGED, "non-finite density or velocity");
+    return SDUGKS_OK;
+}
+
+int sdugks_info(sdugks_t *h, double *dt, double *tau, int64_t *step, int32_t *n_cells)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    if (dt) *dt = h->mb.dt;
+    if (tau) *tau = h->mb.tau;
+    if (step) *step = h->step;
+    if (n_cells) *n_cells = h->mb.nc;
+    return SDUGKS_OK;
+}
+
+int sdugks_destroy(sdugks_t *h)
+{
+    if (!h) return SDUGKS_OK;
+    hipSetDevice(h->device);
+    hipStreamSynchronize(h->stream);
+    if (h->own) hipFree(h->base);
+    hipHostFree(h->host4);
+    delete h;
+    return SDUGKS_OK;
+}
+
+int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i)
+{
+    if (!h || cell < 0 || cell >= h->mb.nc || i < 0 || i > 8) return fail(SDUGKS_EINVAL, "bad poison target");
+    HIPCHK(hipSetDevice(h->device));
+    double *p = h->at<double>(h->L.off_f[h->cur]) + (size_t)i * h->L.np + h->mb.iperm[cell];
+    HIPCHK(launch_poke(p, NAN, h->stream));
+    return sync_check(h);
+}
+
+int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugks_batch_t **out)
+{
+    if (!members || n <= 0 || !out) return fail(SDUGKS_EINVAL, "bad batch arguments");
+    sdugks_batch_t *b = new (std::nothrow) sdugks_batch_t();
+    if (!b) return fail(SDUGKS_ENOMEM, "host allocation failed");
+    b->members.assign(members, members + n);
+    b->stream = (hipStream_t)stream;
+    *out = b;
+    return SDUGKS_OK;
+}
+
+int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
+{
+    if (!b) return fail(SDUGKS_EINVAL, "null batch");
+    for (int64_t k = 0; k < n; k++)
+        for (sdugks_t *h : b->members) {
+            int rc = sdugks_step(h, 1);
+            if (rc) return rc;
+        }
+    return SDUGKS_OK;
+}
+
+int sdugks_batch_destroy(sdugks_batch_t *b)
+{
+    delete b;
+    return SDUGKS_OK;
+}
+
+}  // extern "C"

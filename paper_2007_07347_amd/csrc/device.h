@@ -1,0 +1,55 @@
+// Device-side data of one solver instance and the launchers of its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sdg {
+
+struct DevBC {
+    int32_t type;
+    double rho, u, v;
+};
+
+// Mesh and constants of one instance, as seen by the kernels.  All per-cell
+// arrays are pitched: entry (row r, cell c) at r*np + c.
+struct DevMesh {
+    int32_t nc, np, D, n_bfaces;
+    const int32_t *nbr;                 // [D][np]
+    const double *lnx, *lny;            // [D][np] scaled outward normal
+    const double *rsx, *rsy;            // [D][np] midpoint - own centroid
+    const double *rox, *roy;            // [D][np] midpoint image - neighbour centroid
+    const double *ainv;                 // [3][np] inverse LSQ normal matrix
+    const double *dtv;                  // [np] dt / V
+    const double *area;                 // [np]
+    const int32_t *bf_tag;              // [n_bfaces]
+    const DevBC *bcs;                   // [n_bc]
+    double a, b, c1, lam, dt;           // (2tau-dt)/2tau, dt/2tau, 2tau/(2tau+dt), dt/tau, dt
+};
+
+// FP64 state buffers of one step: read (in) and write (out).
+struct DevState {
+    const double *f, *W, *G;            // [9][np], [3][np], [3][np]
+    double *fo, *Wo, *Go;
+};
+
+struct DevScratch {
+    double *fbp;                        // [9][np] fbar+ at the cell centres
+    double *sg;                         // [18][np] its least-squares gradient (x rows 0..8, y rows 9..17)
+};
+
+// Launchers (stream-ordered, no synchronisation).  Return the hipError_t of the launch.
+hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st);
+hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st);
+// Deterministic reductions of the residual / mass / finiteness check: writes
+// out4 = {sum |u-u_snap|^2, sum |u_snap|^2, sum V rho, count of non-finite}.
+// snap = [2][np] (U, V); update_snap re-snapshots.
+hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int update_snap, double *partials,
+                         double *out4, hipStream_t st);
+// f[i][c] = value (failure injection).
+hipError_t launch_poke(double *p, double value, hipStream_t st);
+
+constexpr int kReduceBlocks = 256;
+
+}  // namespace sdg

@@ -1,0 +1,268 @@
+// gfx950 kernels of one sDUGKS time step (Zhong et al., arXiv:2007.07347,
+// Section II, eleven-step summary), FP64 storage.
+//
+//   k_grad          steps 2-3: fbar+ = a f + b feq(W) at every centre and its
+//                   least-squares gradient (normal equations of the LLSR fit,
+//                   boundary states as points at the face midpoints);
+//                   one thread per (cell, velocity).
+//   k_flux_update   steps 1, 3-11: per face the upwind reconstruction at the
+//                   foot point x_f - e_i dt (Eq. fbpsource), the face macros
+//                   and equilibrium, f at the face (Eq. f_t_n+1), the
+//                   mesoscopic and macroscopic fluxes (Eqs. MesoFlux,
+//                   MacroFlux); per cell the conservative update of W
+//                   (Eq. MacroUpdate), feq^{n+1} and f^{n+1} (Eq. fn+1).
+//                   Four lanes per cell, one face each; the per-cell flux
+//                   sums are formed with lane shuffles in a fixed order.
+//   k_reduce*       residual of the cavity case, total mass, finiteness.
+//
+// Every face is evaluated by both of its cells from bit-identical operands
+// (the mesh builder stores mirrored copies), so the two evaluations agree
+// exactly and each face flux leaves one cell exactly as it enters the other.
+#include "device.h"
+
+#include "d2q9.h"
+
+namespace sdg {
+
+namespace {
+
+// Boundary state (rho_b, u_b) of Section III for a face of the given tag,
+// seen from the adjacent cell with macros (rho, ux, uy).
+__device__ __forceinline__ void boundary_state(const DevBC &bc, double rho, double ux, double uy,
+                                               double &rb, double &ub, double &vb)
+{
+    if (bc.type == 2) { rb = bc.rho; ub = bc.u; vb = bc.v; }          // inlet / far field
+    else if (bc.type == 3) { rb = rho; ub = ux; vb = uy; }            // outlet
+    else { rb = rho; ub = bc.u; vb = bc.v; }                          // wall (moving or at rest)
+}
+
+__global__ void __launch_bounds__(256) k_grad(DevMesh m, DevState s, DevScratch x)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (c >= m.nc) return;
+    const int np = m.np;
+    const double exi = kEx[i], eyi = kEy[i], wi = kW[i];
+    const double rho = s.W[c];
+    const double ux = s.W[np + c] / rho, uy = s.W[2 * np + c] / rho;
+    const double fe = feq_one(wi, exi, eyi, rho, ux, uy);
+    const double fc = s.f[(size_t)i * np + c];
+    const double fb = m.a * fc + m.b * fe;
+    double ax = 0.0, ay = 0.0;
+    for (int sl = 0; sl < m.D; sl++) {
+        const int q = sl * np + c;
+        const int nb = m.nbr[q];
+        if (nb == INT32_MIN) continue;
+        double val, dx, dy;
+        if (nb >= 0) {
+            const double rk = s.W[nb];
+            const double uk = s.W[np + nb] / rk, vk = s.W[2 * np + nb] / rk;
+            val = m.a * s.f[(size_t)i * np + nb] + m.b * feq_one(wi, exi, eyi, rk, uk, vk);
+            dx = m.rsx[q] - m.rox[q];
+            dy = m.rsy[q] - m.roy[q];
+        } else {
+            const DevBC bc = m.bcs[m.bf_tag[-1 - nb]];
+            double rb, ub, vb;
+            boundary_state(bc, rho, ux, uy, rb, ub, vb);
+            val = feq_one(wi, exi, eyi, rb, ub, vb) + m.a * (fc - fe);
+            dx = m.rsx[q];
+            dy = m.rsy[q];
+        }
+        const double df = val - fb;
+        ax += dx * df;
+        ay += dy * df;
+    }
+    const double i0 = m.ainv[c], i1 = m.ainv[np + c], i2 = m.ainv[2 * np + c];
+    x.fbp[(size_t)i * np + c] = fb;
+    x.sg[(size_t)i * np + c] = i0 * ax + i1 * ay;
+    x.sg[(size_t)(9 + i) * np + c] = i1 * ax + i2 * ay;
+}
+
+// Sum over the L lanes of a cell, butterfly order (every lane gets the same bits).
+template <int L>
+__device__ __forceinline__ double lane_sum(double v)
+{
+#pragma unroll
+    for (int off = 1; off < L; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_flux_update(DevMesh m, DevState s, DevScratch x, int lagged)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = t / L;
+    const int sl = t % L;
+    const bool valid = c < m.nc;
+    const int np = m.np;
+    double phi[9], g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; i++) phi[i] = 0.0;
+    const int nb = (valid && sl < m.D) ? m.nbr[sl * np + c] : INT32_MIN;
+    if (nb != INT32_MIN) {
+        const int q = sl * np + c;
+        const double lnx = m.lnx[q], lny = m.lny[q];
+        const double rsx = m.rsx[q], rsy = m.rsy[q];
+        double fbar[9];
+        if (nb >= 0) {
+            const double rox = m.rox[q], roy = m.roy[q];
+#pragma unroll
+            for (int i = 0; i < 9; i++) {
+                const double sn = kEx[i] * lnx + kEy[i] * lny;
+                double rs = 0.0, ro = 0.0;
+                if (sn >= 0.0)
+                    rs = x.fbp[(size_t)i * np + c] + (rsx - m.dt * kEx[i]) * x.sg[(size_t)i * np + c]
+                         + (rsy - m.dt * kEy[i]) * x.sg[(size_t)(9 + i) * np + c];
+                if (sn <= 0.0)
+                    ro = x.fbp[(size_t)i * np + nb] + (rox - m.dt * kEx[i]) * x.sg[(size_t)i * np + nb]
+                         + (roy - m.dt * kEy[i]) * x.sg[(size_t)(9 + i) * np + nb];
+                fbar[i] = sn > 0.0 ? rs : (sn < 0.0 ? ro : 0.5 * (rs + ro));
+            }
+        } else {
+            const double rho = s.W[c];
+            const double ux = s.W[np + c] / rho, uy = s.W[2 * np + c] / rho;
+            const DevBC bc = m.bcs[m.bf_tag[-1 - nb]];
+            double rb, ub, vb;
+            boundary_state(bc, rho, ux, uy, rb, ub, vb);
+#pragma unroll
+            for (int i = 0; i < 9; i++) {
+                const double sn = kEx[i] * lnx + kEy[i] * lny;
+                const double sx = x.sg[(size_t)i * np + c], sy = x.sg[(size_t)(9 + i) * np + c];
+                if (sn >= 0.0) {
+                    fbar[i] = x.fbp[(size_t)i * np + c] + (rsx - m.dt * kEx[i]) * sx + (rsy - m.dt * kEy[i]) * sy;
+                } else {
+                    // incoming: the boundary state's fbar+ carried to the foot point
+                    const double fe = feq_one(kW[i], kEx[i], kEy[i], rho, ux, uy);
+                    const double gb = feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) + m.a * (s.f[(size_t)i * np + c] - fe);
+                    fbar[i] = gb - m.dt * (kEx[i] * sx + kEy[i] * sy);
+                }
+            }
+        }
+        // face macros (step 5), face equilibrium (6), face f (7), fluxes (8, 1)
+        double rf = 0.0, mx = 0.0, my = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; i++) { rf += fbar[i]; mx += kEx[i] * fbar[i]; my += kEy[i] * fbar[i]; }
+        const double uf = mx / rf, vf = my / rf;
+#pragma unroll
+        for (int i = 0; i < 9; i++) {
+            const double sn = kEx[i] * lnx + kEy[i] * lny;
+            const double ff = m.c1 * (fbar[i] + m.b * feq_one(kW[i], kEx[i], kEy[i], rf, uf, vf));
+            phi[i] = sn * ff;
+            g0 += phi[i];
+            g1 += kEx[i] * phi[i];
+            g2 += kEy[i] * phi[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; i++) phi[i] = lane_sum<L>(phi[i]);
+    g0 = lane_sum<L>(g0);
+    g1 = lane_sum<L>(g1);
+    g2 = lane_sum<L>(g2);
+    if (!valid) return;
+    // steps 9-11
+    const double dtv = m.dtv[c];
+    double G0 = g0, G1 = g1, G2 = g2;
+    if (lagged) { G0 = s.G[c]; G1 = s.G[np + c]; G2 = s.G[2 * np + c]; }
+    const double rn = s.W[c] - dtv * G0;
+    const double mxn = s.W[np + c] - dtv * G1;
+    const double myn = s.W[2 * np + c] - dtv * G2;
+    if (sl == 0) s.Wo[c] = rn;
+    if (sl == 1 % L) s.Wo[np + c] = mxn;
+    if (sl == 2 % L) s.Wo[2 * np + c] = myn;
+    if (lagged) {
+        if (sl == 0) s.Go[c] = g0;
+        if (sl == 1 % L) s.Go[np + c] = g1;
+        if (sl == 2 % L) s.Go[2 * np + c] = g2;
+    }
+    const double un = mxn / rn, vn = myn / rn;
+    const double inv = 1.0 / (1.0 + m.lam);
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        if (i % L != sl) continue;
+        const double fe = feq_one(kW[i], kEx[i], kEy[i], rn, un, vn);
+        s.fo[(size_t)i * np + c] = (s.f[(size_t)i * np + c] - dtv * phi[i] + m.lam * fe) * inv;
+    }
+}
+
+// Per-block partial sums in a fixed order; a second single-block pass adds them.
+__global__ void __launch_bounds__(256) k_reduce(int nc, int np, const double *__restrict__ W,
+                                               const double *__restrict__ area, double *snap, int update,
+                                               double *partials)
+{
+    __shared__ double red[4][256];
+    const int chunk = (nc + kReduceBlocks - 1) / kReduceBlocks;
+    const int lo = blockIdx.x * chunk, hi = min(nc, lo + chunk);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int c = lo + threadIdx.x; c < hi; c += blockDim.x) {
+        const double r = W[c];
+        const double U = W[np + c] / r, V = W[2 * np + c] / r;
+        const double su = snap[c], sv = snap[np + c];
+        a0 += (U - su) * (U - su) + (V - sv) * (V - sv);
+        a1 += su * su + sv * sv;
+        a2 += area[c] * r;
+        a3 += (isfinite(r) && isfinite(U) && isfinite(V)) ? 0.0 : 1.0;
+        if (update) { snap[c] = U; snap[np + c] = V; }
+    }
+    red[0][threadIdx.x] = a0; red[1][threadIdx.x] = a1; red[2][threadIdx.x] = a2; red[3][threadIdx.x] = a3;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) partials[threadIdx.x * kReduceBlocks + blockIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) k_reduce_final(const double *partials, double *out4)
+{
+    __shared__ double red[4][kReduceBlocks];
+    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = partials[k * kReduceBlocks + threadIdx.x];
+    __syncthreads();
+    for (int w = kReduceBlocks / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_poke(double *p, double v) { *p = v; }
+
+}  // namespace
+
+hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st)
+{
+    dim3 grid((m.nc + 255) / 256, 9);
+    hipLaunchKernelGGL(k_grad, grid, dim3(256), 0, st, m, s, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st)
+{
+    if (m.D <= 4) {
+        const long threads = (long)m.nc * 4;
+        hipLaunchKernelGGL(k_flux_update<4>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, m, s, x, lagged);
+    } else {
+        const long threads = (long)m.nc * 8;
+        hipLaunchKernelGGL(k_flux_update<8>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, m, s, x, lagged);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int update_snap, double *partials,
+                         double *out4, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(kReduceBlocks), dim3(256), 0, st, m.nc, m.np, W, m.area, snap, update_snap, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceBlocks), 0, st, partials, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_poke(double *p, double value, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_poke, dim3(1), dim3(1), 0, st, p, value);
+    return hipGetLastError();
+}
+
+}  // namespace sdg

@@ -1,0 +1,336 @@
+// Host mesh builder: geometry of Section II of Zhong et al. (arXiv:2007.07347)
+// -- control volumes V_j and their centres, face normals and midpoints (one
+// quadrature point per face for the contour integrals of Eqs. MacroFlux and
+// MesoFlux), the linear least-squares normal matrix of the LLSR gradient, the
+// periodic gluing of Section III -- laid out for the device.
+//
+// Layout decisions (not the paper's): every cell carries D face slots
+// (structure of arrays, padded), each slot holding the face seen from the
+// cell.  Both cells of an interior face store bit-identical copies of the
+// face data (mirrored), so the two evaluate the face flux from identical
+// operands and the flux leaves one cell exactly as it enters the other.
+// Boundary states enter the least-squares system as points at the face
+// midpoints.  Cells are renumbered by reverse Cuthill-McKee for locality.
+#include "mesh.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <deque>
+#include <unordered_map>
+
+namespace sdg {
+
+namespace {
+
+struct HalfEdge {
+    int32_t cell, slot, a, b;
+};
+
+inline uint64_t edge_key(int32_t p, int32_t q)
+{
+    uint32_t lo = (uint32_t)std::min(p, q), hi = (uint32_t)std::max(p, q);
+    return ((uint64_t)lo << 32) | hi;
+}
+
+// Reverse Cuthill-McKee on the cell adjacency graph (CSR adj).
+std::vector<int32_t> rcm_order(int32_t n, const std::vector<int32_t> &ptr, const std::vector<int32_t> &adj)
+{
+    std::vector<int32_t> deg(n), order;
+    order.reserve(n);
+    for (int32_t c = 0; c < n; c++) deg[c] = ptr[c + 1] - ptr[c];
+    std::vector<char> seen(n, 0);
+    std::vector<int32_t> level(n, -1);
+    auto bfs_last = [&](int32_t s) {   // farthest node of a BFS from s (pseudo-peripheral search)
+        std::deque<int32_t> q{s};
+        std::vector<int32_t> touched{s};
+        level[s] = 0;
+        int32_t last = s;
+        while (!q.empty()) {
+            int32_t c = q.front();
+            q.pop_front();
+            last = c;
+            for (int32_t e = ptr[c]; e < ptr[c + 1]; e++) {
+                int32_t k = adj[e];
+                if (level[k] < 0) { level[k] = level[c] + 1; q.push_back(k); touched.push_back(k); }
+            }
+        }
+        int32_t depth = level[last];
+        for (int32_t t : touched) level[t] = -1;
+        return std::make_pair(last, depth);
+    };
+    for (int32_t start = 0; start < n; start++) {
+        if (seen[start]) continue;
+        // pseudo-peripheral start: repeat BFS from the farthest node while the depth grows
+        int32_t s = start;
+        auto r = bfs_last(s);
+        for (int it = 0; it < 4; it++) {
+            auto r2 = bfs_last(r.first);
+            if (r2.second <= r.second) break;
+            s = r.first;
+            r = r2;
+        }
+        std::deque<int32_t> q{s};
+        seen[s] = 1;
+        std::vector<int32_t> nb;
+        while (!q.empty()) {
+            int32_t c = q.front();
+            q.pop_front();
+            order.push_back(c);
+            nb.clear();
+            for (int32_t e = ptr[c]; e < ptr[c + 1]; e++)
+                if (!seen[adj[e]]) { nb.push_back(adj[e]); seen[adj[e]] = 1; }
+            std::sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; });
+            for (int32_t k : nb) q.push_back(k);
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+}  // namespace
+
+int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+               MeshBuild &out, std::string &err)
+{
+    char buf[256];
+#define BAD(...) do { std::snprintf(buf, sizeof buf, __VA_ARGS__); err = buf; return SDUGKS_EINVAL; } while (0)
+    if (!m || !prm) BAD("null mesh or params");
+    const int32_t nc = m->n_cells, nn = m->n_nodes;
+    if (nc <= 0 || nn <= 0 || !m->node_xy || !m->cell_ptr || !m->cell_nodes) BAD("empty mesh");
+    if (m->n_bedges < 0 || (m->n_bedges > 0 && (!m->bedge_nodes || !m->bedge_tag))) BAD("bad boundary edge arrays");
+    if (n_bc < 0 || (n_bc > 0 && !bc)) BAD("bad boundary-condition table");
+    if (m->cell_ptr[0] != 0) BAD("cell_ptr[0] must be 0");
+    const double *xy = m->node_xy;
+
+    // ---- per-cell geometry in caller order: fan triangulation about the vertex mean
+    std::vector<double> area(nc), cx(nc), cy(nc);
+    int32_t D = 0;
+    for (int32_t c = 0; c < nc; c++) {
+        int32_t p0 = m->cell_ptr[c], deg = m->cell_ptr[c + 1] - p0;
+        if (deg < 3 || deg > 8) BAD("cell %d has %d nodes (3..8 supported)", c, deg);
+        D = std::max(D, deg);
+        double mx = 0, my = 0;
+        for (int32_t k = 0; k < deg; k++) {
+            int32_t v = m->cell_nodes[p0 + k];
+            if (v < 0 || v >= nn) BAD("cell %d references node %d", c, v);
+            mx += xy[2 * v];
+            my += xy[2 * v + 1];
+        }
+        mx /= deg;
+        my /= deg;
+        double A = 0, Sx = 0, Sy = 0;
+        for (int32_t k = 0; k < deg; k++) {
+            int32_t v = m->cell_nodes[p0 + k], w = m->cell_nodes[p0 + (k + 1) % deg];
+            double ax = xy[2 * v] - mx, ay = xy[2 * v + 1] - my, bx = xy[2 * w] - mx, by = xy[2 * w + 1] - my;
+            double t = 0.5 * (ax * by - ay * bx);      // signed area of (mean, v, w)
+            A += t;
+            Sx += t * (ax + bx) / 3.0;
+            Sy += t * (ay + by) / 3.0;
+        }
+        if (!(A > 0)) BAD("cell %d is not counter-clockwise (signed area %g)", c, A);
+        area[c] = A;
+        cx[c] = mx + Sx / A;
+        cy[c] = my + Sy / A;
+    }
+
+    // ---- match edges
+    std::unordered_map<uint64_t, int32_t> first;   // edge -> half edge index awaiting its twin
+    std::vector<HalfEdge> he;
+    he.reserve(m->cell_ptr[nc]);
+    struct Face { int32_t o, n, os, ns, tag; double lnx, lny, xm, ym, tx, ty; };
+    std::vector<Face> faces;
+    faces.reserve(m->cell_ptr[nc]);
+    std::vector<int32_t> slot_face((size_t)nc * D, -1);   // caller order [c*D + s]
+    auto make_face = [&](const HalfEdge &o, int32_t n, int32_t ns, int32_t tag, double tx, double ty) {
+        Face f;
+        f.o = o.cell; f.os = o.slot; f.n = n; f.ns = ns; f.tag = tag;
+        double xa = xy[2 * o.a], ya = xy[2 * o.a + 1], xb = xy[2 * o.b], yb = xy[2 * o.b + 1];
+        f.lnx = yb - ya;
+        f.lny = xa - xb;
+        f.xm = 0.5 * (xa + xb);
+        f.ym = 0.5 * (ya + yb);
+        f.tx = tx; f.ty = ty;
+        faces.push_back(f);
+        int32_t id = (int32_t)faces.size() - 1;
+        slot_face[(size_t)o.cell * D + o.slot] = id;
+        if (n >= 0) slot_face[(size_t)n * D + ns] = id;
+    };
+    for (int32_t c = 0; c < nc; c++) {
+        int32_t p0 = m->cell_ptr[c], deg = m->cell_ptr[c + 1] - p0;
+        for (int32_t k = 0; k < deg; k++) {
+            HalfEdge h{c, k, m->cell_nodes[p0 + k], m->cell_nodes[p0 + (k + 1) % deg]};
+            if (h.a == h.b) BAD("cell %d has a repeated node", c);
+            uint64_t key = edge_key(h.a, h.b);
+            auto it = first.find(key);
+            if (it == first.end()) { first.emplace(key, (int32_t)he.size()); he.push_back(h); continue; }
+            int32_t j = it->second;
+            if (j < 0) BAD("edge (%d,%d) is shared by more than two cells", h.a, h.b);
+            const HalfEdge &g = he[j];
+            if (g.a != h.b || g.b != h.a) BAD("cells %d and %d traverse edge (%d,%d) the same way", g.cell, c, h.a, h.b);
+            if (g.cell == c) BAD("cell %d uses edge (%d,%d) twice", c, h.a, h.b);
+            make_face(g, c, k, -1, 0.0, 0.0);
+            it->second = -1;
+        }
+    }
+    // boundary edges: each must close an unmatched half edge
+    struct BEdge { int32_t he, tag; double mx, my; };
+    std::vector<BEdge> bed(m->n_bedges);
+    std::unordered_map<uint64_t, int32_t> bseen;
+    for (int32_t e = 0; e < m->n_bedges; e++) {
+        int32_t p = m->bedge_nodes[2 * e], q = m->bedge_nodes[2 * e + 1], t = m->bedge_tag[e];
+        if (t < 0 || t >= n_bc) BAD("boundary edge %d has tag %d (table has %d)", e, t, n_bc);
+        uint64_t key = edge_key(p, q);
+        auto it = first.find(key);
+        if (it == first.end() || it->second < 0) BAD("boundary edge %d (%d,%d) is not a free cell edge", e, p, q);
+        if (!bseen.emplace(key, e).second) BAD("boundary edge %d listed twice", e);
+        const HalfEdge &h = he[it->second];
+        bed[e] = {it->second, t, 0.5 * (xy[2 * h.a] + xy[2 * h.b]), 0.5 * (xy[2 * h.a + 1] + xy[2 * h.b + 1])};
+    }
+    if ((size_t)m->n_bedges != bseen.size()) BAD("duplicate boundary edges");
+    for (auto &kv : first)
+        if (kv.second >= 0 && !bseen.count(kv.first)) BAD("cell %d has an untagged free edge", he[kv.second].cell);
+    for (int32_t t = 0; t < n_bc; t++) {
+        int32_t ty = bc[t].type;
+        if (ty < SDUGKS_BC_WALL || ty > SDUGKS_BC_PERIODIC) BAD("bc %d: unknown type %d", t, ty);
+        if (ty == SDUGKS_BC_INLET && !(bc[t].rho > 0)) BAD("bc %d: inlet density must be positive", t);
+        if (ty == SDUGKS_BC_PERIODIC) {
+            int32_t p = bc[t].partner;
+            if (p < 0 || p >= n_bc || p == t || bc[p].type != SDUGKS_BC_PERIODIC || bc[p].partner != t) BAD("bc %d: bad periodic partner", t);
+            double tol = 1e-12 * (1.0 + std::fabs(bc[t].shift_x) + std::fabs(bc[t].shift_y));
+            if (std::fabs(bc[t].shift_x + bc[p].shift_x) > tol || std::fabs(bc[t].shift_y + bc[p].shift_y) > tol)
+                BAD("bc %d: partner shift is not the opposite translation", t);
+        }
+    }
+    // plain boundary faces
+    std::vector<int32_t> bf_cell_c, bf_tag_c;   // caller order of cells
+    for (int32_t e = 0; e < m->n_bedges; e++) {
+        if (bc[bed[e].tag].type == SDUGKS_BC_PERIODIC) continue;
+        make_face(he[bed[e].he], -1, -1, bed[e].tag, 0.0, 0.0);
+    }
+    // periodic gluing: sort each partner side by midpoint, look targets up with a tolerance
+    double ext = 0;
+    for (int32_t v = 0; v < nn; v++) ext = std::max(ext, std::fabs(xy[2 * v]) + std::fabs(xy[2 * v + 1]));
+    const double tol = 1e-9 * (1.0 + ext);
+    std::vector<char> glued(m->n_bedges, 0);
+    for (int32_t t = 0; t < n_bc; t++) {
+        if (bc[t].type != SDUGKS_BC_PERIODIC || bc[t].partner < t) continue;
+        int32_t p = bc[t].partner;
+        std::vector<int32_t> side_p;
+        for (int32_t e = 0; e < m->n_bedges; e++) if (bed[e].tag == p) side_p.push_back(e);
+        std::sort(side_p.begin(), side_p.end(), [&](int32_t x, int32_t y) { return bed[x].mx < bed[y].mx; });
+        for (int32_t e = 0; e < m->n_bedges; e++) {
+            if (bed[e].tag != t) continue;
+            double gx = bed[e].mx + bc[t].shift_x, gy = bed[e].my + bc[t].shift_y;
+            auto lo = std::lower_bound(side_p.begin(), side_p.end(), gx - tol,
+                                       [&](int32_t x, double v) { return bed[x].mx < v; });
+            int32_t hit = -1;
+            for (auto it = lo; it != side_p.end() && bed[*it].mx <= gx + tol; ++it)
+                if (!glued[*it] && std::fabs(bed[*it].my - gy) <= tol) { hit = *it; break; }
+            if (hit < 0) BAD("periodic edge %d (tag %d) has no partner on tag %d", e, t, p);
+            glued[e] = glued[hit] = 1;
+            const HalfEdge &ht = he[bed[e].he], &hp = he[bed[hit].he];
+            // the edge of tag t owns the face; its neighbour sits at x - shift_t seen from it
+            make_face(ht, hp.cell, hp.slot, t, bc[t].shift_x, bc[t].shift_y);
+        }
+    }
+    for (int32_t e = 0; e < m->n_bedges; e++)
+        if (bc[bed[e].tag].type == SDUGKS_BC_PERIODIC && !glued[e]) BAD("periodic edge %d left unglued", e);
+
+    // ---- cell order
+    std::vector<int32_t> perm(nc), iperm(nc);
+    if (prm->reorder) {
+        std::vector<int32_t> ptr(nc + 1, 0), adj;
+        for (const Face &f : faces)
+            if (f.n >= 0 && f.n != f.o) { ptr[f.o + 1]++; ptr[f.n + 1]++; }
+        for (int32_t c = 0; c < nc; c++) ptr[c + 1] += ptr[c];
+        adj.resize(ptr[nc]);
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (const Face &f : faces)
+            if (f.n >= 0 && f.n != f.o) { adj[fill[f.o]++] = f.n; adj[fill[f.n]++] = f.o; }
+        perm = rcm_order(nc, ptr, adj);
+    } else {
+        for (int32_t c = 0; c < nc; c++) perm[c] = c;
+    }
+    for (int32_t k = 0; k < nc; k++) iperm[perm[k]] = k;
+
+    // ---- slot arrays in internal order
+    out.nc = nc; out.D = D; out.n_faces = (int32_t)faces.size();
+    out.perm = perm; out.iperm = iperm;
+    out.area.resize(nc); out.cx.resize(nc); out.cy.resize(nc); out.ainv.assign(3 * (size_t)nc, 0.0);
+    size_t ns = (size_t)D * nc;
+    out.nbr.assign(ns, kEmptySlot);
+    out.lnx.assign(ns, 0); out.lny.assign(ns, 0); out.rsx.assign(ns, 0); out.rsy.assign(ns, 0);
+    out.rox.assign(ns, 0); out.roy.assign(ns, 0);
+    out.bf_cell.clear(); out.bf_tag.clear();
+    std::vector<int32_t> bf_index(faces.size(), -1);
+    for (size_t fi = 0; fi < faces.size(); fi++)
+        if (faces[fi].n < 0) {
+            bf_index[fi] = (int32_t)out.bf_cell.size();
+            out.bf_cell.push_back(iperm[faces[fi].o]);
+            out.bf_tag.push_back(faces[fi].tag);
+        }
+    out.n_bfaces = (int32_t)out.bf_cell.size();
+    double hmin = INFINITY;
+    out.n_singular = 0;
+    for (int32_t k = 0; k < nc; k++) {
+        int32_t c = perm[k];
+        out.area[k] = area[c]; out.cx[k] = cx[c]; out.cy[k] = cy[c];
+        int32_t deg = m->cell_ptr[c + 1] - m->cell_ptr[c];
+        double sxx = 0, sxy = 0, syy = 0, hc = INFINITY;
+        for (int32_t s = 0; s < deg; s++) {
+            const Face &f = faces[slot_face[(size_t)c * D + s]];
+            size_t q = (size_t)s * nc + k;
+            bool own = (f.o == c && f.os == s);
+            // face data from the owner's side: midpoint, its image on the neighbour side
+            double ro_x = f.xm - cx[f.o], ro_y = f.ym - cy[f.o];
+            double rn_x = 0, rn_y = 0;
+            if (f.n >= 0) { rn_x = (f.xm + f.tx) - cx[f.n]; rn_y = (f.ym + f.ty) - cy[f.n]; }
+            double dx, dy;
+            if (f.n < 0) {
+                out.nbr[q] = -(1 + bf_index[slot_face[(size_t)c * D + s]]);
+                out.lnx[q] = f.lnx; out.lny[q] = f.lny;
+                out.rsx[q] = ro_x; out.rsy[q] = ro_y;
+                dx = ro_x; dy = ro_y;                         // boundary point at the face midpoint
+            } else if (own) {
+                out.nbr[q] = iperm[f.n];
+                out.lnx[q] = f.lnx; out.lny[q] = f.lny;
+                out.rsx[q] = ro_x; out.rsy[q] = ro_y; out.rox[q] = rn_x; out.roy[q] = rn_y;
+                dx = ro_x - rn_x; dy = ro_y - rn_y;
+            } else {
+                out.nbr[q] = iperm[f.o];
+                out.lnx[q] = -f.lnx; out.lny[q] = -f.lny;
+                out.rsx[q] = rn_x; out.rsy[q] = rn_y; out.rox[q] = ro_x; out.roy[q] = ro_y;
+                dx = rn_x - ro_x; dy = rn_y - ro_y;
+            }
+            sxx += dx * dx; sxy += dx * dy; syy += dy * dy;
+            double l = std::sqrt(out.lnx[q] * out.lnx[q] + out.lny[q] * out.lny[q]);
+            double dist = std::fabs(out.rsx[q] * out.lnx[q] + out.rsy[q] * out.lny[q]) / l;
+            hc = std::min(hc, 2.0 * dist);
+        }
+        hmin = std::min(hmin, hc);
+        double det = sxx * syy - sxy * sxy, tr = sxx + syy;
+        if (std::fabs(det) > 1e-12 * tr * tr) {
+            out.ainv[k] = syy / det;
+            out.ainv[(size_t)nc + k] = -sxy / det;
+            out.ainv[2 * (size_t)nc + k] = sxx / det;
+        } else {
+            out.n_singular++;
+        }
+    }
+    out.bcs.resize(n_bc);
+    for (int32_t t = 0; t < n_bc; t++) out.bcs[t] = {bc[t].type, bc[t].rho, bc[t].u, bc[t].v};
+
+    // ---- time scales
+    out.h_min = hmin;
+    double tau = prm->tau > 0 ? prm->tau : prm->nu / (1.0 / 3.0);
+    if (!(tau > 0) || !std::isfinite(tau)) BAD("need tau > 0 or nu > 0");
+    double dt = prm->dt > 0 ? prm->dt : prm->cfl * hmin / std::sqrt(2.0);
+    if (!(dt > 0) || !std::isfinite(dt)) BAD("need dt > 0 or cfl > 0");
+    out.tau = tau;
+    out.dt = dt;
+    return SDUGKS_OK;
+#undef BAD
+}
+
+}  // namespace sdg

@@ -1,0 +1,48 @@
+// Host-side mesh builder of the solver library: raw polygons -> per-cell slot
+// arrays in the library's (optionally RCM) order.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sdugks.h"
+
+namespace sdg {
+
+constexpr int32_t kEmptySlot = INT32_MIN;   // padding slot of a cell with fewer faces than D
+
+struct BcEntry {
+    int32_t type;
+    double rho, u, v;
+};
+
+// Everything the device needs, in the library's cell order.  Per-slot arrays
+// are structure-of-arrays [D][nc]: slot s of cell c at index s*nc + c.
+struct MeshBuild {
+    int32_t nc = 0;        // cells
+    int32_t D = 0;         // slots per cell (max polygon degree)
+    int32_t n_faces = 0;   // faces after periodic gluing
+    int32_t n_bfaces = 0;  // boundary (non-periodic) faces
+    int32_t n_singular = 0;
+    double h_min = 0, dt = 0, tau = 0;
+    std::vector<int32_t> perm;    // internal index -> caller index
+    std::vector<int32_t> iperm;   // caller index -> internal index
+    // per cell, internal order
+    std::vector<double> area, cx, cy;
+    std::vector<double> ainv;     // [3][nc]: (A^-1)_xx, (A^-1)_xy, (A^-1)_yy of the LSQ normal matrix
+    // per slot
+    std::vector<int32_t> nbr;     // >= 0 neighbour cell; < 0: -(1 + boundary face); kEmptySlot
+    std::vector<double> lnx, lny; // scaled outward normal l*n of the face, seen from this cell
+    std::vector<double> rsx, rsy; // face midpoint minus this cell's centroid
+    std::vector<double> rox, roy; // face midpoint (in the neighbour's frame) minus the neighbour's centroid
+    // boundary faces
+    std::vector<int32_t> bf_cell, bf_tag;
+    std::vector<BcEntry> bcs;
+};
+
+// Returns SDUGKS_OK or an error code with a message in err.
+int build_mesh(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+               MeshBuild &out, std::string &err);
+
+}  // namespace sdg

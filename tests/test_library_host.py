@@ -1,0 +1,126 @@
+"""Host-side checks of libsdugks.so that need no GPU: the library loads and
+exports every function include/sdugks.h declares, the host mesh builder
+agrees with the oracle's geometry, and invalid input is rejected with an
+error code and message instead of a crash."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import meshgen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2007_07347_amd import sdugks
+    return sdugks
+
+
+def test_header_symbols_are_exported(lib):
+    src = open(os.path.join(ROOT, "include", "sdugks.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char \*)\s*(sdugks_\w+)\s*\(", src, flags=re.M))
+    assert len(declared) >= 17
+    for name in declared:
+        assert hasattr(lib._lib, name), name
+    assert declared == set(lib.EXPORTED)
+
+
+CASES = {
+    "couette": lambda: meshgen.couette(4, 32),
+    "cavity": lambda: meshgen.cavity(48),
+    "ogrid": lambda: meshgen.cylinder_ogrid(40, 25, seed=3),
+    "periodic_tri": lambda: meshgen.jittered_periodic_triangles(8, seed=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_geometry_matches_oracle(lib, oracle_mod, name):
+    mesh, bcs = CASES[name]()
+    g = lib.geometry(mesh, bcs, nu=0.01, cfl=0.5)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
+    go = o.geometry()
+    assert g["n_faces"] == o.n_faces
+    assert g["dt"] == pytest.approx(o.dt, rel=1e-14)
+    assert g["tau"] == pytest.approx(o.tau, rel=1e-15)
+    assert g["h_min"] == pytest.approx(o.h_min, rel=1e-14)
+    scale = max(1.0, np.abs(go["cx"]).max())
+    np.testing.assert_allclose(g["area"], go["area"], rtol=1e-12)
+    assert np.abs(g["cx"] - go["cx"]).max() <= 1e-14 * scale
+    assert np.abs(g["cy"] - go["cy"]).max() <= 1e-14 * scale
+    assert sorted(g["perm"].tolist()) == list(range(o.n_cells))
+
+
+def test_rcm_reduces_bandwidth(lib):
+    """Reverse Cuthill-McKee on a shuffled structured mesh brings face
+    neighbours close in the internal order."""
+    mesh, bcs = meshgen.cavity(32)
+    mesh2, _ = meshgen.relabel(mesh, seed=3)
+    g = lib.geometry(mesh2, bcs, nu=0.01, cfl=0.5)
+    inv = np.empty_like(g["perm"])
+    inv[g["perm"]] = np.arange(len(inv))
+    o_cells = mesh2["cell_nodes"].reshape(-1, 4)
+    # bandwidth over shared edges
+    edges = {}
+    bw_new = bw_old = 0
+    for c, poly in enumerate(o_cells):
+        for k in range(4):
+            key = tuple(sorted((poly[k], poly[(k + 1) % 4])))
+            if key in edges:
+                d = edges[key]
+                bw_old = max(bw_old, abs(c - d))
+                bw_new = max(bw_new, abs(inv[c] - inv[d]))
+            else:
+                edges[key] = c
+    assert bw_new <= 64 < bw_old
+
+
+def test_dt_and_tau_overrides(lib):
+    mesh, bcs = meshgen.couette(4, 8)
+    g = lib.geometry(mesh, bcs, nu=0.01, cfl=0.5, dt=0.02, tau=0.7)
+    assert g["dt"] == 0.02 and g["tau"] == 0.7
+    g = lib.geometry(mesh, bcs, nu=0.02, cfl=0.25)
+    assert g["tau"] == pytest.approx(0.06, rel=1e-15)
+    assert g["dt"] == pytest.approx(0.25 * (1 / 8) / math.sqrt(2), rel=1e-15)
+
+
+def _expect_einval(lib, mesh, bcs, text, **kw):
+    with pytest.raises(lib.SdugksError) as ei:
+        lib.geometry(mesh, bcs, **{"nu": 0.01, "cfl": 0.5, **kw})
+    assert ei.value.code == lib.EINVAL
+    assert text in str(ei.value)
+
+
+def test_invalid_inputs_are_rejected(lib):
+    mesh, bcs = meshgen.cavity(4)
+    bad = dict(mesh)
+    bad["cell_nodes"] = mesh["cell_nodes"].reshape(-1, 4)[:, ::-1].ravel().copy()   # clockwise
+    _expect_einval(lib, bad, bcs, "counter-clockwise")
+    bad = dict(mesh)
+    bad["bedge_tag"] = mesh["bedge_tag"].copy()
+    bad["bedge_tag"][0] = 7
+    _expect_einval(lib, bad, bcs, "tag")
+    bad = dict(mesh)
+    bad["bedge_nodes"] = mesh["bedge_nodes"][1:].copy()
+    bad["bedge_tag"] = mesh["bedge_tag"][1:].copy()
+    _expect_einval(lib, bad, bcs, "untagged")
+    _expect_einval(lib, mesh, bcs, "tau", nu=0.0)
+    m2, b2 = meshgen.couette(4, 8)
+    b2 = [dict(b) for b in b2]
+    b2[2]["shift"] = (0.3, 0.0)
+    _expect_einval(lib, m2, b2, "opposite translation")
+    b2 = [dict(b) for b in meshgen.couette(4, 8)[1]]
+    b2[2]["shift"] = (0.3, 0.0)
+    b2[3]["shift"] = (-0.3, 0.0)
+    _expect_einval(lib, m2, b2, "no partner")
+    with pytest.raises(lib.SdugksError):
+        lib.geometry(mesh, bcs, nu=0.01, cfl=0.5, precision=5)
+
+
+def test_state_bytes_scales_with_cells(lib):
+    b1 = lib.state_bytes(*meshgen.cavity(32), nu=0.01)
+    b2 = lib.state_bytes(*meshgen.cavity(64), nu=0.01)
+    assert 3.5 < b2 / b1 < 4.5
