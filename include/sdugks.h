@@ -92,8 +92,12 @@ typedef struct {
     double rho0, u0, v0;          /* initial uniform equilibrium; rho0 is also the FP32DEV offset */
     int32_t precision;            /* SDUGKS_FP64 or SDUGKS_FP32DEV */
     int32_t macro_flux;           /* SDUGKS_MACRO_CURRENT (default) or SDUGKS_MACRO_LAGGED */
-    int32_t reorder;              /* 1 = reverse Cuthill-McKee cell order inside the library */
+    int32_t reorder;              /* two-kernel step: 1 = reverse Cuthill-McKee cell order inside the
+                                     library (the fused step orders cells tile by tile instead) */
     int32_t residual_interval;    /* steps between residual checks in serving loops (paper: 1000) */
+    int32_t tile_cells;           /* fused one-kernel step over tiles of at most this many cells
+                                     (0 = library default, -1 = two-kernel step without tiles) */
+    int32_t block_threads;        /* threads per workgroup of the fused step: 64, 128 or 256 (0 = default) */
 } sdugks_params;
 
 typedef struct sdugks_s sdugks_t;
@@ -106,6 +110,13 @@ typedef struct sdugks_s sdugks_t;
 int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
                     double *dt, double *tau, double *h_min, int32_t *n_faces,
                     double *area, double *cx, double *cy, int32_t *perm);
+
+/* Host-only: how the fused step would tile this mesh.  tile_cells: the tile
+ * size used (0 when the two-kernel step is used: polygons with more than four
+ * faces, or tile_cells = -1); n_tiles; max_local: largest tile plus both halo
+ * rings; max_ring1: largest tile plus its first ring.  Outputs may be NULL. */
+int sdugks_tiling(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                  int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1);
 
 /* Device bytes a handle for this problem needs (all state, geometry and
  * scratch); the size of a caller workspace.  Host only. */

@@ -1,0 +1,78 @@
+"""Autotuner of the fused step's schedule: tile size (cells per workgroup,
+which sets the halo overhead and the LDS per workgroup, hence how many
+workgroups share a compute unit) and threads per workgroup (which sets how
+many lanes serve each cell in every phase).
+
+Each candidate is built with the library, warmed up, and timed with HIP
+events over a fixed number of steps on the instance's own stream; the
+fastest is returned and cached on disk per mesh signature, so a serving loop
+or a batch tunes once per mesh class.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from . import sdugks
+
+CANDIDATES = [(t, b) for t in (16, 32, 64, 128) for b in (64, 128, 256) if b <= 4 * t * 2]
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+
+def signature(mesh, precision):
+    """Mesh class key: cell count, polygon degrees and a hash of the connectivity."""
+    h = hashlib.sha1()
+    h.update(np.ascontiguousarray(mesh["cell_ptr"]).tobytes())
+    h.update(np.ascontiguousarray(mesh["cell_nodes"]).tobytes())
+    return f"{len(mesh['cell_ptr']) - 1}-{precision}-{h.hexdigest()[:12]}"
+
+
+def _load_cache(path):
+    try:
+        with open(path) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def time_candidate(mesh, bcs, tile_cells, block_threads, steps=200, warmup=20, **kw):
+    import torch
+    s = sdugks.Solver(mesh, bcs, tile_cells=tile_cells, block_threads=block_threads, **kw)
+    s.step(warmup)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s.stream)
+    s.step(steps)
+    b.record(s.stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / steps
+    s.close()
+    return ms
+
+
+def autotune(mesh, bcs, candidates=None, steps=200, cache=CACHE, refresh=False, **kw):
+    """Return ({"tile_cells", "block_threads"}, table) for the fastest fused
+    schedule of this mesh; table lists ms per step of every candidate."""
+    key = signature(mesh, kw.get("precision", sdugks.FP64))
+    db = _load_cache(cache) if cache else {}
+    if not refresh and key in db:
+        return db[key]["best"], db[key]["table"]
+    table = []
+    for t, b in (candidates or CANDIDATES):
+        try:
+            ms = time_candidate(mesh, bcs, t, b, steps=steps, **kw)
+        except sdugks.SdugksError as e:        # e.g. a tile too small for the mesh degree
+            table.append({"tile_cells": t, "block_threads": b, "ms": None, "error": str(e)})
+            continue
+        table.append({"tile_cells": t, "block_threads": b, "ms": ms})
+    ok = [r for r in table if r["ms"] is not None]
+    best = min(ok, key=lambda r: r["ms"])
+    best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
+    if cache:
+        db[key] = {"best": best, "table": table}
+        with open(cache + ".tmp", "w") as fh:
+            json.dump(db, fh, indent=1)
+        os.replace(cache + ".tmp", cache)
+    return best, table

@@ -41,6 +41,7 @@ struct Layout {
     size_t off_f[2]{}, off_W[2]{}, off_G[2]{}, off_fbp = 0, off_sg = 0, off_snap = 0;
     size_t off_nbr = 0, off_geo = 0, off_ainv = 0, off_dtv = 0, off_area = 0, off_bft = 0, off_bcs = 0;
     size_t off_part = 0, off_out = 0, total = 0;
+    size_t off_thdr = 0, off_hlist = 0, off_ladj = 0;
 };
 
 Layout make_layout(const MeshBuild &mb)
@@ -55,8 +56,15 @@ Layout make_layout(const MeshBuild &mb)
         L.off_W[k] = take(3 * row);
         L.off_G[k] = take(3 * row);
     }
-    L.off_fbp = take(9 * row);
-    L.off_sg = take(18 * row);
+    if (mb.n_tiles > 0) {
+        // fused step: fbar+ and its gradient live in LDS only
+        L.off_thdr = take(mb.tile_hdr.size() * sizeof(int32_t));
+        L.off_hlist = take(std::max<size_t>(1, mb.hlist.size()) * sizeof(int32_t));
+        L.off_ladj = take(mb.ladj.size() * sizeof(int16_t));
+    } else {
+        L.off_fbp = take(9 * row);
+        L.off_sg = take(18 * row);
+    }
     L.off_snap = take(2 * row);
     L.off_nbr = take((size_t)mb.D * L.np * sizeof(int32_t));
     L.off_geo = take(6 * (size_t)mb.D * row);
@@ -85,7 +93,9 @@ struct sdugks_s {
     bool diverged = false;
     int precision = SDUGKS_FP64, macro = SDUGKS_MACRO_CURRENT;
     double rho0 = 1.0;
+    int block = 256;
     DevMesh dm{};
+    DevTiles dt{};
     double *host4 = nullptr;     // pinned, 4 doubles
 
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
@@ -113,6 +123,8 @@ int check_prm(const sdugks_params *prm)
     if (prm->macro_flux != SDUGKS_MACRO_CURRENT && prm->macro_flux != SDUGKS_MACRO_LAGGED)
         return fail(SDUGKS_EINVAL, "macro_flux must be SDUGKS_MACRO_CURRENT or SDUGKS_MACRO_LAGGED");
     if (!(prm->rho0 > 0)) return fail(SDUGKS_EINVAL, "rho0 must be positive");
+    if (prm->block_threads != 0 && prm->block_threads != 64 && prm->block_threads != 128 && prm->block_threads != 256)
+        return fail(SDUGKS_EINVAL, "block_threads must be 0, 64, 128 or 256");
     return SDUGKS_OK;
 }
 
@@ -168,9 +180,13 @@ int reduce(sdugks_t *h, int update_snap, double out[4])
 int enqueue_step(sdugks_t *h)
 {
     DevState s = h->state();
-    DevScratch x = h->scratch();
-    HIPCHK(launch_grad(h->dm, s, x, h->stream));
-    HIPCHK(launch_flux_update(h->dm, s, x, h->macro == SDUGKS_MACRO_LAGGED, h->stream));
+    if (h->mb.n_tiles > 0) {
+        HIPCHK(launch_step_tiled(h->dm, h->dt, s, h->macro == SDUGKS_MACRO_LAGGED, h->block, h->stream));
+    } else {
+        DevScratch x = h->scratch();
+        HIPCHK(launch_grad(h->dm, s, x, h->stream));
+        HIPCHK(launch_flux_update(h->dm, s, x, h->macro == SDUGKS_MACRO_LAGGED, h->stream));
+    }
     h->cur ^= 1;
     h->step++;
     return SDUGKS_OK;
@@ -203,6 +219,19 @@ int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, 
     return SDUGKS_OK;
 }
 
+int sdugks_tiling(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
+                  int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1)
+{
+    MeshBuild mb;
+    int rc = build(mesh, bc, n_bc, prm, mb);
+    if (rc) return rc;
+    if (tile_cells) *tile_cells = mb.tile_T;
+    if (n_tiles) *n_tiles = mb.n_tiles;
+    if (max_local) *max_local = mb.nl_max;
+    if (max_ring1) *max_ring1 = mb.na_max;
+    return SDUGKS_OK;
+}
+
 int sdugks_state_bytes(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
                        size_t *bytes)
 {
@@ -232,6 +261,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         return fail(SDUGKS_ENODEV, "the current device is not gfx950");
     }
     h->stream = (hipStream_t)stream;
+    h->block = prm->block_threads ? prm->block_threads : 256;
     h->precision = prm->precision;
     h->macro = prm->macro_flux;
     h->rho0 = prm->rho0;
@@ -289,6 +319,18 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         for (size_t t = 0; t < bcs.size(); t++) bcs[t] = {mb.bcs[t].type, mb.bcs[t].rho, mb.bcs[t].u, mb.bcs[t].v};
         if (!bcs.empty() && hipMemcpy(h->at<DevBC>(L.off_bcs), bcs.data(), bcs.size() * sizeof(DevBC), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(SDUGKS_EHIP, "upload of the boundary table failed"));
+    }
+    if (mb.n_tiles > 0) {
+        if (hipMemcpy(h->at<int32_t>(L.off_thdr), mb.tile_hdr.data(), mb.tile_hdr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+            (!mb.hlist.empty() && hipMemcpy(h->at<int32_t>(L.off_hlist), mb.hlist.data(), mb.hlist.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) ||
+            hipMemcpy(h->at<int16_t>(L.off_ladj), mb.ladj.data(), mb.ladj.size() * sizeof(int16_t), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(SDUGKS_EHIP, "upload of the tile tables failed"));
+        h->dt.n_tiles = mb.n_tiles;
+        h->dt.nl_max = mb.nl_max;
+        h->dt.na_max = mb.na_max;
+        h->dt.hdr = h->at<int32_t>(L.off_thdr);
+        h->dt.hlist = h->at<int32_t>(L.off_hlist);
+        h->dt.ladj = h->at<int16_t>(L.off_ladj);
     }
     DevMesh &d = h->dm;
     d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces;
@@ -415,33 +457,43 @@ int sdugks_step(sdugks_t *h, int64_t n)
 int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **names, int32_t max_kernels,
                          int32_t *n_kernels)
 {
-    if (!h || !avg_ms || max_kernels < 2 || !n_kernels) return fail(SDUGKS_EINVAL, "bad arguments");
+    if (!h || !avg_ms || max_kernels < 2 || !n_kernels || n < 0) return fail(SDUGKS_EINVAL, "bad arguments");
     if (h->diverged) return fail(SDUGKS_EDIVERGED, "state is not finite");
     HIPCHK(hipSetDevice(h->device));
+    const bool tiled = h->mb.n_tiles > 0;
+    const int nk = tiled ? 1 : 2;
     hipEvent_t ev[3];
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     double acc[2] = {0, 0};
     for (int64_t k = 0; k < n; k++) {
         DevState s = h->state();
-        DevScratch x = h->scratch();
+        const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
         HIPCHK(hipEventRecord(ev[0], h->stream));
-        HIPCHK(launch_grad(h->dm, s, x, h->stream));
-        HIPCHK(hipEventRecord(ev[1], h->stream));
-        HIPCHK(launch_flux_update(h->dm, s, x, h->macro == SDUGKS_MACRO_LAGGED, h->stream));
-        HIPCHK(hipEventRecord(ev[2], h->stream));
-        HIPCHK(hipEventSynchronize(ev[2]));
+        if (tiled) {
+            HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->block, h->stream));
+            HIPCHK(hipEventRecord(ev[1], h->stream));
+        } else {
+            DevScratch x = h->scratch();
+            HIPCHK(launch_grad(h->dm, s, x, h->stream));
+            HIPCHK(hipEventRecord(ev[1], h->stream));
+            HIPCHK(launch_flux_update(h->dm, s, x, lagged, h->stream));
+            HIPCHK(hipEventRecord(ev[2], h->stream));
+        }
+        HIPCHK(hipEventSynchronize(ev[nk]));
         float a = 0, b = 0;
         HIPCHK(hipEventElapsedTime(&a, ev[0], ev[1]));
-        HIPCHK(hipEventElapsedTime(&b, ev[1], ev[2]));
+        if (!tiled) HIPCHK(hipEventElapsedTime(&b, ev[1], ev[2]));
         acc[0] += a; acc[1] += b;
         h->cur ^= 1;
         h->step++;
     }
     for (auto &e : ev) hipEventDestroy(e);
-    avg_ms[0] = n ? acc[0] / n : 0;
-    avg_ms[1] = n ? acc[1] / n : 0;
-    if (names) { names[0] = "k_grad"; names[1] = "k_flux_update"; }
-    *n_kernels = 2;
+    for (int k = 0; k < nk; k++) avg_ms[k] = n ? acc[k] / n : 0;
+    if (names) {
+        if (tiled) names[0] = "k_step_tiled";
+        else { names[0] = "k_grad"; names[1] = "k_flux_update"; }
+    }
+    *n_kernels = nk;
     return SDUGKS_OK;
 }
 

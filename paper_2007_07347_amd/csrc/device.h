@@ -34,6 +34,15 @@ struct DevState {
     double *fo, *Wo, *Go;
 };
 
+// Tiles of the fused step (see MeshBuild): headers [n_tiles][8], halo lists,
+// local adjacency; nl_max / na_max size the LDS arrays.
+struct DevTiles {
+    int32_t n_tiles, nl_max, na_max;
+    const int32_t *hdr;
+    const int32_t *hlist;
+    const int16_t *ladj;
+};
+
 struct DevScratch {
     double *fbp;                        // [9][np] fbar+ at the cell centres
     double *sg;                         // [18][np] its least-squares gradient (x rows 0..8, y rows 9..17)
@@ -42,6 +51,10 @@ struct DevScratch {
 // Launchers (stream-ordered, no synchronisation).  Return the hipError_t of the launch.
 hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st);
 hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st);
+// Fused one-kernel step over tiles (D <= 4 slots per cell).
+hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int block,
+                             hipStream_t st);
+size_t step_tiled_lds_bytes(const DevTiles &t);
 // Deterministic reductions of the residual / mass / finiteness check: writes
 // out4 = {sum |u-u_snap|^2, sum |u_snap|^2, sum V rho, count of non-finite}.
 // snap = [2][np] (U, V); update_snap re-snapshots.

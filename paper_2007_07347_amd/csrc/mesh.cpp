@@ -10,7 +10,10 @@
 // face data (mirrored), so the two evaluate the face flux from identical
 // operands and the flux leaves one cell exactly as it enters the other.
 // Boundary states enter the least-squares system as points at the face
-// midpoints.  Cells are renumbered by reverse Cuthill-McKee for locality.
+// midpoints.  Cells are renumbered for locality: into compact tiles by
+// recursive coordinate bisection for the fused one-kernel step (each tile
+// with its two halo rings and a local adjacency table), or by reverse
+// Cuthill-McKee for the two-kernel step.
 #include "mesh.h"
 
 #include <algorithm>
@@ -86,6 +89,84 @@ std::vector<int32_t> rcm_order(int32_t n, const std::vector<int32_t> &ptr, const
     }
     std::reverse(order.begin(), order.end());
     return order;
+}
+
+// Recursive coordinate bisection of ids[lo, hi) into k parts of near-equal
+// size, split across the longer side of the bounding box of the centroids.
+void rcb(std::vector<int32_t> &ids, size_t lo, size_t hi, int64_t k, const std::vector<double> &cx,
+         const std::vector<double> &cy, std::vector<std::pair<size_t, size_t>> &parts)
+{
+    if (k <= 1 || hi - lo <= 1) { parts.emplace_back(lo, hi); return; }
+    double x0 = INFINITY, x1 = -INFINITY, y0 = INFINITY, y1 = -INFINITY;
+    for (size_t j = lo; j < hi; j++) {
+        x0 = std::min(x0, cx[ids[j]]); x1 = std::max(x1, cx[ids[j]]);
+        y0 = std::min(y0, cy[ids[j]]); y1 = std::max(y1, cy[ids[j]]);
+    }
+    const bool by_x = (x1 - x0) >= (y1 - y0);
+    const int64_t kl = k / 2;
+    const size_t n = hi - lo, nl = (size_t)((int64_t)n * kl / k);
+    auto key = [&](int32_t c) { return by_x ? std::make_tuple(cx[c], cy[c], c) : std::make_tuple(cy[c], cx[c], c); };
+    std::nth_element(ids.begin() + lo, ids.begin() + lo + nl, ids.begin() + hi,
+                     [&](int32_t a, int32_t b) { return key(a) < key(b); });
+    rcb(ids, lo, lo + nl, kl, cx, cy, parts);
+    rcb(ids, lo + nl, hi, k - kl, cx, cy, parts);
+}
+
+// Tiles of the fused step over the internal order (tile-major already).
+void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &parts)
+{
+    const int32_t nc = out.nc, D = out.D;
+    out.n_tiles = (int32_t)parts.size();
+    out.tile_hdr.assign((size_t)out.n_tiles * 8, 0);
+    out.hlist.clear();
+    out.ladj.clear();
+    out.nl_max = out.na_max = 0;
+    std::vector<int32_t> stamp(nc, -1), loc(nc, -1);
+    std::vector<int32_t> h1, h2;
+    for (int32_t t = 0; t < out.n_tiles; t++) {
+        const int32_t g0 = (int32_t)parts[t].first, nt = (int32_t)(parts[t].second - parts[t].first);
+        for (int32_t k = 0; k < nt; k++) { stamp[g0 + k] = t; loc[g0 + k] = k; }
+        h1.clear(); h2.clear();
+        // cells stamped t are already local; a ring collects the unstamped
+        // face neighbours of a set of cells and stamps them
+        auto ring = [&](int32_t c, std::vector<int32_t> &dst) {
+            for (int32_t s = 0; s < D; s++) {
+                const int32_t nb = out.nbr[(size_t)s * nc + c];
+                if (nb >= 0 && stamp[nb] != t) { stamp[nb] = t; dst.push_back(nb); }
+            }
+        };
+        for (int32_t k = 0; k < nt; k++) ring(g0 + k, h1);
+        std::sort(h1.begin(), h1.end());
+        for (int32_t c : h1) ring(c, h2);
+        std::sort(h2.begin(), h2.end());
+        const int32_t n1 = (int32_t)h1.size(), n2 = (int32_t)h2.size(), na = nt + n1;
+        for (int32_t k = 0; k < n1; k++) loc[h1[k]] = nt + k;
+        for (int32_t k = 0; k < n2; k++) loc[h2[k]] = na + k;
+        int32_t *h = &out.tile_hdr[(size_t)t * 8];
+        h[0] = g0; h[1] = nt; h[2] = n1; h[3] = n2;
+        h[4] = (int32_t)out.hlist.size();
+        h[5] = (int32_t)out.ladj.size();
+        out.hlist.insert(out.hlist.end(), h1.begin(), h1.end());
+        out.hlist.insert(out.hlist.end(), h2.begin(), h2.end());
+        const size_t a0 = out.ladj.size();
+        out.ladj.resize(a0 + (size_t)D * na);
+        for (int32_t k = 0; k < na; k++) {
+            const int32_t c = k < nt ? g0 + k : h1[k - nt];
+            for (int32_t s = 0; s < D; s++) {
+                const int32_t nb = out.nbr[(size_t)s * nc + c];
+                int16_t v;
+                if (nb == kEmptySlot) v = -2;
+                else if (nb < 0) v = -1;
+                else v = (int16_t)loc[nb];
+                out.ladj[a0 + (size_t)s * na + k] = v;
+            }
+        }
+        out.nl_max = std::max(out.nl_max, na + n2);
+        out.na_max = std::max(out.na_max, na);
+        for (int32_t k = 0; k < nt; k++) { stamp[g0 + k] = -1; loc[g0 + k] = -1; }
+        for (int32_t c : h1) { stamp[c] = -1; loc[c] = -1; }
+        for (int32_t c : h2) { stamp[c] = -1; loc[c] = -1; }
+    }
 }
 
 }  // namespace
@@ -237,9 +318,16 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     for (int32_t e = 0; e < m->n_bedges; e++)
         if (bc[bed[e].tag].type == SDUGKS_BC_PERIODIC && !glued[e]) BAD("periodic edge %d left unglued", e);
 
-    // ---- cell order
+    // ---- cell order: tile-major (fused step) or reverse Cuthill-McKee
     std::vector<int32_t> perm(nc), iperm(nc);
-    if (prm->reorder) {
+    const bool tiled = prm->tile_cells >= 0 && D <= 4;
+    int32_t T = prm->tile_cells > 0 ? prm->tile_cells : kDefaultTile;
+    if (tiled && (T < 8 || T > 4096)) BAD("tile_cells must be in [8, 4096] (or 0 / -1)");
+    std::vector<std::pair<size_t, size_t>> parts;
+    if (tiled) {
+        for (int32_t c = 0; c < nc; c++) perm[c] = c;
+        rcb(perm, 0, nc, ((int64_t)nc + T - 1) / T, cx, cy, parts);
+    } else if (prm->reorder) {
         std::vector<int32_t> ptr(nc + 1, 0), adj;
         for (const Face &f : faces)
             if (f.n >= 0 && f.n != f.o) { ptr[f.o + 1]++; ptr[f.n + 1]++; }
@@ -320,6 +408,19 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     }
     out.bcs.resize(n_bc);
     for (int32_t t = 0; t < n_bc; t++) out.bcs[t] = {bc[t].type, bc[t].rho, bc[t].u, bc[t].v};
+    out.tile_T = 0; out.n_tiles = 0;
+    out.tile_hdr.clear(); out.hlist.clear(); out.ladj.clear();
+    if (tiled) {
+        build_tiles(out, parts);
+        if (tile_lds_bytes(out.nl_max, out.na_max) > kTileLdsLimit) {
+            // halos too large for one workgroup's LDS: bisect into smaller tiles
+            if (T <= 8) BAD("mesh too irregular for the fused step's LDS tiles");
+            sdugks_params smaller = *prm;
+            smaller.tile_cells = T / 2;
+            return build_mesh(m, bc, n_bc, &smaller, out, err);
+        }
+        out.tile_T = T;
+    }
 
     // ---- time scales
     out.h_min = hmin;

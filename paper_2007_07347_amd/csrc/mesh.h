@@ -39,7 +39,22 @@ struct MeshBuild {
     // boundary faces
     std::vector<int32_t> bf_cell, bf_tag;
     std::vector<BcEntry> bcs;
+    // tiles of the fused step (empty when the two-kernel step is used).  Tile t
+    // owns the contiguous internal cells [g0, g0 + nt); its local index space is
+    // those cells, then the n1 cells of its first halo ring, then the n2 of its
+    // second ring (global ids in hlist).  ladj holds, for every local cell of the
+    // tile and its first ring, the local index of the neighbour behind each slot
+    // (-1: boundary face, -2: empty slot), [D][nt + n1] per tile.
+    int32_t tile_T = 0, n_tiles = 0, nl_max = 0, na_max = 0;
+    std::vector<int32_t> tile_hdr;   // [n_tiles][8]: g0, nt, n1, n2, hoff, aoff, 0, 0
+    std::vector<int32_t> hlist;
+    std::vector<int16_t> ladj;
 };
+
+// LDS bytes of one workgroup of the fused FP64 step for the given maxima.
+inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max) { return (12 * (size_t)nl_max + 18 * (size_t)na_max) * 8; }
+constexpr size_t kTileLdsLimit = 64 * 1024;
+constexpr int32_t kDefaultTile = 128;
 
 // Returns SDUGKS_OK or an error code with a message in err.
 int build_mesh(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,

@@ -90,19 +90,27 @@ def _small_cases():
     }
 
 
+PATHS = {"fused": dict(tile_cells=0), "fused_t32_b64": dict(tile_cells=32, block_threads=64),
+         "two_kernel": dict(tile_cells=-1)}
+
+
 @pytest.mark.parametrize("name", sorted(_small_cases()))
 @pytest.mark.parametrize("macro", [1, 0])
-def test_random_state_window(sd, oracle_mod, name, macro):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_random_state_window(sd, oracle_mod, name, macro, path):
     """A seeded generic state (every term of the step active) advanced 40
     steps on ragged small meshes covering walls, a moving lid, far-field inlet,
     outlet, periodic gluing, triangles, hexagons (eight lanes per cell) and a
-    shuffled cell order; both macroscopic-flux readings."""
+    shuffled cell order; both macroscopic-flux readings; the fused tiled step
+    (two tile shapes) and the two-kernel step."""
     build, kw = _small_cases()[name]
+    kw = dict(kw, **PATHS[path])
     mesh, bcs = build()
     if macro == 0:
         kw = dict(kw, tau=0.0, cfl=0.2)
-    say("window", name, "macro", macro)
-    o = oracle_mod.Oracle(mesh, bcs, macro=macro, **kw)
+    say("window", name, "macro", macro, "path", path)
+    okw = {k: v for k, v in kw.items() if k not in ("tile_cells", "block_threads")}
+    o = oracle_mod.Oracle(mesh, bcs, macro=macro, **okw)
     if macro == 0 and o.dt > 2.0 * o.tau:
         pytest.skip("lagged flux is unstable at this dt/tau")
     g = sd.Solver(mesh, bcs, macro=macro, **kw)
@@ -145,6 +153,22 @@ def test_cylinder_200k_window(sd, oracle_mod):
     g.step(12)
     o.step(12)
     compare(g, o, "cylinder200k")
+
+
+def test_fused_and_two_kernel_paths_agree(sd):
+    """The fused tiled step and the two-kernel step on the full 200k-cell
+    cylinder mesh, several tile shapes: equal to rounding after 50 steps."""
+    mesh, bcs = meshgen.cylinder_ogrid(400, 250, seed=0)
+    kw = dict(nu=0.0025, cfl=0.5, u0=0.1)
+    ref = sd.Solver(mesh, bcs, tile_cells=-1, **kw)
+    ref.step(50)
+    fr, Wr, _ = ref.state()
+    for tc, bt in ((0, 256), (64, 128), (32, 64), (128, 64)):
+        say("fused", tc, bt, sd.tiling(mesh, bcs, tile_cells=tc, **kw))
+        g = sd.Solver(mesh, bcs, tile_cells=tc, block_threads=bt, **kw)
+        g.step(50)
+        f, W, _ = g.state()
+        assert rel_linf(f, fr) <= 1e-13 and rel_linf(W, Wr) <= 1e-13
 
 
 def test_residual_and_mass_match_oracle(sd, oracle_mod):

@@ -59,7 +59,7 @@ def test_rcm_reduces_bandwidth(lib):
     neighbours close in the internal order."""
     mesh, bcs = meshgen.cavity(32)
     mesh2, _ = meshgen.relabel(mesh, seed=3)
-    g = lib.geometry(mesh2, bcs, nu=0.01, cfl=0.5)
+    g = lib.geometry(mesh2, bcs, nu=0.01, cfl=0.5, tile_cells=-1)
     inv = np.empty_like(g["perm"])
     inv[g["perm"]] = np.arange(len(inv))
     o_cells = mesh2["cell_nodes"].reshape(-1, 4)
@@ -76,6 +76,19 @@ def test_rcm_reduces_bandwidth(lib):
             else:
                 edges[key] = c
     assert bw_new <= 64 < bw_old
+
+
+def test_tiles_are_compact(lib):
+    """Bisection tiles of a structured mesh are near-square blocks: on the
+    256^2 cavity a 128-cell tile has at most 2*(8+16) first-ring cells."""
+    mesh, bcs = meshgen.cavity(256)
+    t = lib.tiling(mesh, bcs, nu=1e-4)
+    assert t["tile_cells"] == 128 and t["n_tiles"] == 512
+    assert t["max_ring1"] <= 128 + 48 and t["max_local"] <= 128 + 48 + 52
+    t = lib.tiling(*meshgen.hexagon_strip(5, 4), nu=0.01)
+    assert t["tile_cells"] == 0          # six faces per cell: two-kernel step
+    t = lib.tiling(*meshgen.cavity(64), nu=0.01, tile_cells=-1)
+    assert t["n_tiles"] == 0
 
 
 def test_dt_and_tau_overrides(lib):
