@@ -18,7 +18,8 @@ import numpy as np
 
 from . import sdugks
 
-CANDIDATES = [(t, b) for t in (16, 32, 64, 128) for b in (64, 128, 256) if b <= 4 * t * 2]
+# (tile cells, threads): a tile holds at most a quarter as many cells as threads
+CANDIDATES = [(16, 64), (16, 128), (32, 128), (16, 256), (32, 256), (64, 256)]
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 

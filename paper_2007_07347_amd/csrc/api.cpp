@@ -41,7 +41,7 @@ struct Layout {
     size_t off_f[2]{}, off_W[2]{}, off_G[2]{}, off_fbp = 0, off_sg = 0, off_snap = 0;
     size_t off_nbr = 0, off_geo = 0, off_ainv = 0, off_dtv = 0, off_area = 0, off_bft = 0, off_bcs = 0;
     size_t off_part = 0, off_out = 0, total = 0;
-    size_t off_thdr = 0, off_hlist = 0, off_ladj = 0;
+    size_t off_thdr = 0, off_lgid = 0, off_ladj = 0, off_lw = 0;
 };
 
 Layout make_layout(const MeshBuild &mb)
@@ -59,8 +59,9 @@ Layout make_layout(const MeshBuild &mb)
     if (mb.n_tiles > 0) {
         // fused step: fbar+ and its gradient live in LDS only
         L.off_thdr = take(mb.tile_hdr.size() * sizeof(int32_t));
-        L.off_hlist = take(std::max<size_t>(1, mb.hlist.size()) * sizeof(int32_t));
+        L.off_lgid = take(mb.lgid.size() * sizeof(int32_t));
         L.off_ladj = take(mb.ladj.size() * sizeof(int16_t));
+        L.off_lw = take(mb.lw.size() * sizeof(double));
     } else {
         L.off_fbp = take(9 * row);
         L.off_sg = take(18 * row);
@@ -321,16 +322,21 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
             return cleanup(fail(SDUGKS_EHIP, "upload of the boundary table failed"));
     }
     if (mb.n_tiles > 0) {
-        if (hipMemcpy(h->at<int32_t>(L.off_thdr), mb.tile_hdr.data(), mb.tile_hdr.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-            (!mb.hlist.empty() && hipMemcpy(h->at<int32_t>(L.off_hlist), mb.hlist.data(), mb.hlist.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) ||
-            hipMemcpy(h->at<int16_t>(L.off_ladj), mb.ladj.data(), mb.ladj.size() * sizeof(int16_t), hipMemcpyHostToDevice) != hipSuccess)
+        auto up = [&](size_t off, const void *src, size_t bytes) {
+            return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+        };
+        if (!up(L.off_thdr, mb.tile_hdr.data(), mb.tile_hdr.size() * sizeof(int32_t)) ||
+            !up(L.off_lgid, mb.lgid.data(), mb.lgid.size() * sizeof(int32_t)) ||
+            !up(L.off_ladj, mb.ladj.data(), mb.ladj.size() * sizeof(int16_t)) ||
+            !up(L.off_lw, mb.lw.data(), mb.lw.size() * sizeof(double)))
             return cleanup(fail(SDUGKS_EHIP, "upload of the tile tables failed"));
         h->dt.n_tiles = mb.n_tiles;
         h->dt.nl_max = mb.nl_max;
         h->dt.na_max = mb.na_max;
         h->dt.hdr = h->at<int32_t>(L.off_thdr);
-        h->dt.hlist = h->at<int32_t>(L.off_hlist);
+        h->dt.lgid = h->at<int32_t>(L.off_lgid);
         h->dt.ladj = h->at<int16_t>(L.off_ladj);
+        h->dt.lw = h->at<double>(L.off_lw);
     }
     DevMesh &d = h->dm;
     d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces;

@@ -34,13 +34,15 @@ struct DevState {
     double *fo, *Wo, *Go;
 };
 
-// Tiles of the fused step (see MeshBuild): headers [n_tiles][8], halo lists,
-// local adjacency; nl_max / na_max size the LDS arrays.
+// Tiles of the fused step (see MeshBuild): headers [n_tiles][8] (g0, nt, n1,
+// n2), and the padded per-tile tables lgid [PL], ladj [D][PA], lw [D][2][PA]
+// with PL = nl_max, PA = na_max.
 struct DevTiles {
     int32_t n_tiles, nl_max, na_max;
     const int32_t *hdr;
-    const int32_t *hlist;
+    const int32_t *lgid;
     const int16_t *ladj;
+    const double *lw;
 };
 
 struct DevScratch {
@@ -64,5 +66,6 @@ hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int up
 hipError_t launch_poke(double *p, double value, hipStream_t st);
 
 constexpr int kReduceBlocks = 256;
+constexpr int kXcds = 8;           // accelerator complex dies of an MI355X, each with its own L2
 
 }  // namespace sdg

@@ -113,19 +113,20 @@ void rcb(std::vector<int32_t> &ids, size_t lo, size_t hi, int64_t k, const std::
 }
 
 // Tiles of the fused step over the internal order (tile-major already).
+// Every per-tile table is padded to the largest tile so tile t's block starts
+// at t times a fixed pitch.
 void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &parts)
 {
     const int32_t nc = out.nc, D = out.D;
     out.n_tiles = (int32_t)parts.size();
     out.tile_hdr.assign((size_t)out.n_tiles * 8, 0);
-    out.hlist.clear();
-    out.ladj.clear();
+    std::vector<std::vector<int32_t>> locals(out.n_tiles);
+    std::vector<int32_t> stamp(nc, -1), h1, h2;
     out.nl_max = out.na_max = 0;
-    std::vector<int32_t> stamp(nc, -1), loc(nc, -1);
-    std::vector<int32_t> h1, h2;
+    // pass 1: halo rings of every tile
     for (int32_t t = 0; t < out.n_tiles; t++) {
         const int32_t g0 = (int32_t)parts[t].first, nt = (int32_t)(parts[t].second - parts[t].first);
-        for (int32_t k = 0; k < nt; k++) { stamp[g0 + k] = t; loc[g0 + k] = k; }
+        for (int32_t k = 0; k < nt; k++) stamp[g0 + k] = t;
         h1.clear(); h2.clear();
         // cells stamped t are already local; a ring collects the unstamped
         // face neighbours of a set of cells and stamps them
@@ -139,33 +140,40 @@ void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &p
         std::sort(h1.begin(), h1.end());
         for (int32_t c : h1) ring(c, h2);
         std::sort(h2.begin(), h2.end());
-        const int32_t n1 = (int32_t)h1.size(), n2 = (int32_t)h2.size(), na = nt + n1;
-        for (int32_t k = 0; k < n1; k++) loc[h1[k]] = nt + k;
-        for (int32_t k = 0; k < n2; k++) loc[h2[k]] = na + k;
+        std::vector<int32_t> &L = locals[t];
+        for (int32_t k = 0; k < nt; k++) L.push_back(g0 + k);
+        L.insert(L.end(), h1.begin(), h1.end());
+        L.insert(L.end(), h2.begin(), h2.end());
         int32_t *h = &out.tile_hdr[(size_t)t * 8];
-        h[0] = g0; h[1] = nt; h[2] = n1; h[3] = n2;
-        h[4] = (int32_t)out.hlist.size();
-        h[5] = (int32_t)out.ladj.size();
-        out.hlist.insert(out.hlist.end(), h1.begin(), h1.end());
-        out.hlist.insert(out.hlist.end(), h2.begin(), h2.end());
-        const size_t a0 = out.ladj.size();
-        out.ladj.resize(a0 + (size_t)D * na);
+        h[0] = g0; h[1] = nt; h[2] = (int32_t)h1.size(); h[3] = (int32_t)h2.size();
+        out.nl_max = std::max(out.nl_max, (int32_t)L.size());
+        out.na_max = std::max(out.na_max, nt + h[2]);
+    }
+    // pass 2: padded tables
+    const size_t PL = out.nl_max, PA = out.na_max;
+    out.lgid.assign((size_t)out.n_tiles * PL, 0);
+    out.ladj.assign((size_t)out.n_tiles * D * PA, -1);
+    out.lw.assign((size_t)out.n_tiles * D * 2 * PA, 0.0);
+    std::vector<int32_t> loc(nc, -1);
+    for (int32_t t = 0; t < out.n_tiles; t++) {
+        const std::vector<int32_t> &L = locals[t];
+        const int32_t na = out.tile_hdr[(size_t)t * 8 + 1] + out.tile_hdr[(size_t)t * 8 + 2];
+        for (size_t k = 0; k < L.size(); k++) { loc[L[k]] = (int32_t)k; out.lgid[t * PL + k] = L[k]; }
         for (int32_t k = 0; k < na; k++) {
-            const int32_t c = k < nt ? g0 + k : h1[k - nt];
+            const int32_t c = L[k];
             for (int32_t s = 0; s < D; s++) {
-                const int32_t nb = out.nbr[(size_t)s * nc + c];
+                const size_t q = (size_t)s * nc + c;
+                const int32_t nb = out.nbr[q];
                 int16_t v;
-                if (nb == kEmptySlot) v = -2;
-                else if (nb < 0) v = -1;
+                if (nb == kEmptySlot) v = -1;
+                else if (nb < 0) v = (int16_t)(-2 - out.bf_tag[-1 - nb]);
                 else v = (int16_t)loc[nb];
-                out.ladj[a0 + (size_t)s * na + k] = v;
+                out.ladj[((size_t)t * D + s) * PA + k] = v;
+                out.lw[(((size_t)t * D + s) * 2 + 0) * PA + k] = out.wx[q];
+                out.lw[(((size_t)t * D + s) * 2 + 1) * PA + k] = out.wy[q];
             }
         }
-        out.nl_max = std::max(out.nl_max, na + n2);
-        out.na_max = std::max(out.na_max, na);
-        for (int32_t k = 0; k < nt; k++) { stamp[g0 + k] = -1; loc[g0 + k] = -1; }
-        for (int32_t c : h1) { stamp[c] = -1; loc[c] = -1; }
-        for (int32_t c : h2) { stamp[c] = -1; loc[c] = -1; }
+        for (int32_t c : L) loc[c] = -1;
     }
 }
 
@@ -321,8 +329,9 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     // ---- cell order: tile-major (fused step) or reverse Cuthill-McKee
     std::vector<int32_t> perm(nc), iperm(nc);
     const bool tiled = prm->tile_cells >= 0 && D <= 4;
-    int32_t T = prm->tile_cells > 0 ? prm->tile_cells : kDefaultTile;
-    if (tiled && (T < 8 || T > 4096)) BAD("tile_cells must be in [8, 4096] (or 0 / -1)");
+    const int32_t B = prm->block_threads > 0 ? prm->block_threads : kDefaultBlock;
+    int32_t T = prm->tile_cells > 0 ? std::min(prm->tile_cells, B / 4) : B / 4;
+    if (tiled && T < 4) BAD("tile_cells must be at least 4 (or 0 / -1)");
     std::vector<std::pair<size_t, size_t>> parts;
     if (tiled) {
         for (int32_t c = 0; c < nc; c++) perm[c] = c;
@@ -350,6 +359,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     out.nbr.assign(ns, kEmptySlot);
     out.lnx.assign(ns, 0); out.lny.assign(ns, 0); out.rsx.assign(ns, 0); out.rsy.assign(ns, 0);
     out.rox.assign(ns, 0); out.roy.assign(ns, 0);
+    out.wx.assign(ns, 0); out.wy.assign(ns, 0);
     out.bf_cell.clear(); out.bf_tag.clear();
     std::vector<int32_t> bf_index(faces.size(), -1);
     for (size_t fi = 0; fi < faces.size(); fi++)
@@ -399,9 +409,18 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
         hmin = std::min(hmin, hc);
         double det = sxx * syy - sxy * sxy, tr = sxx + syy;
         if (std::fabs(det) > 1e-12 * tr * tr) {
-            out.ainv[k] = syy / det;
-            out.ainv[(size_t)nc + k] = -sxy / det;
-            out.ainv[2 * (size_t)nc + k] = sxx / det;
+            const double i0 = syy / det, i1 = -sxy / det, i2 = sxx / det;
+            out.ainv[k] = i0;
+            out.ainv[(size_t)nc + k] = i1;
+            out.ainv[2 * (size_t)nc + k] = i2;
+            // least-squares weights A^-1 d of every stencil point
+            for (int32_t s = 0; s < deg; s++) {
+                const size_t q = (size_t)s * nc + k;
+                const double dx = out.nbr[q] < 0 ? out.rsx[q] : out.rsx[q] - out.rox[q];
+                const double dy = out.nbr[q] < 0 ? out.rsy[q] : out.rsy[q] - out.roy[q];
+                out.wx[q] = i0 * dx + i1 * dy;
+                out.wy[q] = i1 * dx + i2 * dy;
+            }
         } else {
             out.n_singular++;
         }
@@ -409,12 +428,12 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     out.bcs.resize(n_bc);
     for (int32_t t = 0; t < n_bc; t++) out.bcs[t] = {bc[t].type, bc[t].rho, bc[t].u, bc[t].v};
     out.tile_T = 0; out.n_tiles = 0;
-    out.tile_hdr.clear(); out.hlist.clear(); out.ladj.clear();
+    out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lw.clear();
     if (tiled) {
         build_tiles(out, parts);
-        if (tile_lds_bytes(out.nl_max, out.na_max) > kTileLdsLimit) {
-            // halos too large for one workgroup's LDS: bisect into smaller tiles
-            if (T <= 8) BAD("mesh too irregular for the fused step's LDS tiles");
+        if (tile_lds_bytes(out.nl_max, out.na_max) > kTileLdsLimit || out.nl_max > B) {
+            // one thread per local cell and LDS for all of them: bisect into smaller tiles
+            if (T <= 4) BAD("mesh too irregular for the fused step's tiles");
             sdugks_params smaller = *prm;
             smaller.tile_cells = T / 2;
             return build_mesh(m, bc, n_bc, &smaller, out, err);

@@ -36,25 +36,31 @@ struct MeshBuild {
     std::vector<double> lnx, lny; // scaled outward normal l*n of the face, seen from this cell
     std::vector<double> rsx, rsy; // face midpoint minus this cell's centroid
     std::vector<double> rox, roy; // face midpoint (in the neighbour's frame) minus the neighbour's centroid
+    std::vector<double> wx, wy;   // least-squares weight A^-1 d of the stencil point behind the slot
     // boundary faces
     std::vector<int32_t> bf_cell, bf_tag;
     std::vector<BcEntry> bcs;
-    // tiles of the fused step (empty when the two-kernel step is used).  Tile t
-    // owns the contiguous internal cells [g0, g0 + nt); its local index space is
-    // those cells, then the n1 cells of its first halo ring, then the n2 of its
-    // second ring (global ids in hlist).  ladj holds, for every local cell of the
-    // tile and its first ring, the local index of the neighbour behind each slot
-    // (-1: boundary face, -2: empty slot), [D][nt + n1] per tile.
+    // Tiles of the fused step (empty when the two-kernel step is used).  Tile t
+    // owns the contiguous internal cells [g0, g0 + nt); its local cells are
+    // those, then the n1 cells of its first halo ring, then the n2 of its
+    // second.  Per-tile tables, padded to the largest tile (PL = nl_max local
+    // cells, PA = na_max cells of tile + first ring):
+    //   lgid [n_tiles][PL]          internal id of every local cell;
+    //   ladj [n_tiles][D][PA]       neighbour behind each slot of a tile or
+    //                               first-ring cell: local index >= 0, -1 empty,
+    //                               -2 - tag for a boundary face of that tag;
+    //   lw   [n_tiles][D][2][PA]    its least-squares weight (x, y).
     int32_t tile_T = 0, n_tiles = 0, nl_max = 0, na_max = 0;
-    std::vector<int32_t> tile_hdr;   // [n_tiles][8]: g0, nt, n1, n2, hoff, aoff, 0, 0
-    std::vector<int32_t> hlist;
+    std::vector<int32_t> tile_hdr;   // [n_tiles][8]: g0, nt, n1, n2, 0...
+    std::vector<int32_t> lgid;
     std::vector<int16_t> ladj;
+    std::vector<double> lw;
 };
 
 // LDS bytes of one workgroup of the fused FP64 step for the given maxima.
-inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max) { return (12 * (size_t)nl_max + 18 * (size_t)na_max) * 8; }
+inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max) { return (14 * (size_t)nl_max + 18 * (size_t)na_max) * 8; }
 constexpr size_t kTileLdsLimit = 64 * 1024;
-constexpr int32_t kDefaultTile = 128;
+constexpr int32_t kDefaultBlock = 256;   // threads of the fused step; tiles hold at most a quarter as many cells
 
 // Returns SDUGKS_OK or an error code with a message in err.
 int build_mesh(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,

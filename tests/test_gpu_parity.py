@@ -90,7 +90,7 @@ def _small_cases():
     }
 
 
-PATHS = {"fused": dict(tile_cells=0), "fused_t32_b64": dict(tile_cells=32, block_threads=64),
+PATHS = {"fused": dict(tile_cells=0), "fused_t16_b64": dict(tile_cells=16, block_threads=64),
          "two_kernel": dict(tile_cells=-1)}
 
 
@@ -163,7 +163,7 @@ def test_fused_and_two_kernel_paths_agree(sd):
     ref = sd.Solver(mesh, bcs, tile_cells=-1, **kw)
     ref.step(50)
     fr, Wr, _ = ref.state()
-    for tc, bt in ((0, 256), (64, 128), (32, 64), (128, 64)):
+    for tc, bt in ((0, 256), (32, 128), (16, 64), (32, 256)):
         say("fused", tc, bt, sd.tiling(mesh, bcs, tile_cells=tc, **kw))
         g = sd.Solver(mesh, bcs, tile_cells=tc, block_threads=bt, **kw)
         g.step(50)

@@ -80,11 +80,16 @@ def test_rcm_reduces_bandwidth(lib):
 
 def test_tiles_are_compact(lib):
     """Bisection tiles of a structured mesh are near-square blocks: on the
-    256^2 cavity a 128-cell tile has at most 2*(8+16) first-ring cells."""
+    256^2 cavity the default 64-cell tiles (a quarter of the 256 threads of a
+    workgroup) are 8x8 or 4x16 blocks (the stretched mesh splits unevenly), so
+    at most 40 first-ring cells, and every local cell fits one thread."""
     mesh, bcs = meshgen.cavity(256)
     t = lib.tiling(mesh, bcs, nu=1e-4)
-    assert t["tile_cells"] == 128 and t["n_tiles"] == 512
-    assert t["max_ring1"] <= 128 + 48 and t["max_local"] <= 128 + 48 + 52
+    assert t["tile_cells"] == 64 and t["n_tiles"] == 1024
+    assert t["max_ring1"] <= 64 + 40 and t["max_local"] <= 256
+    for tc, bt in ((16, 64), (32, 128), (200, 256)):
+        t = lib.tiling(mesh, bcs, nu=1e-4, tile_cells=tc, block_threads=bt)
+        assert t["tile_cells"] <= bt // 4 and t["max_local"] <= bt
     t = lib.tiling(*meshgen.hexagon_strip(5, 4), nu=0.01)
     assert t["tile_cells"] == 0          # six faces per cell: two-kernel step
     t = lib.tiling(*meshgen.cavity(64), nu=0.01, tile_cells=-1)
