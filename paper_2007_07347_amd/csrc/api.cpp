@@ -44,15 +44,20 @@ struct Layout {
     size_t off_thdr = 0, off_lgid = 0, off_ladj = 0, off_lw = 0;
 };
 
-Layout make_layout(const MeshBuild &mb)
+// What the three step forms need: the two-kernel step keeps fbar+ and its
+// gradient in memory with per-cell neighbour lists and inverse normal
+// matrices; the fused step keeps its tile tables instead; the deviation form
+// stores f and the face geometry in FP32.
+Layout make_layout(const MeshBuild &mb, int precision)
 {
     Layout L;
     L.np = ((size_t)mb.nc + 63) / 64 * 64;
-    const size_t row = L.np * sizeof(double);
+    const bool dev = precision == SDUGKS_FP32DEV;
+    const size_t row = L.np * sizeof(double), rowf = L.np * (dev ? sizeof(float) : sizeof(double));
     size_t p = 0;
     auto take = [&](size_t bytes) { size_t o = p; p += align_up(bytes); return o; };
     for (int k = 0; k < 2; k++) {
-        L.off_f[k] = take(9 * row);
+        L.off_f[k] = take(9 * rowf);
         L.off_W[k] = take(3 * row);
         L.off_G[k] = take(3 * row);
     }
@@ -61,18 +66,18 @@ Layout make_layout(const MeshBuild &mb)
         L.off_thdr = take(mb.tile_hdr.size() * sizeof(int32_t));
         L.off_lgid = take(mb.lgid.size() * sizeof(int32_t));
         L.off_ladj = take(mb.ladj.size() * sizeof(int16_t));
-        L.off_lw = take(mb.lw.size() * sizeof(double));
+        L.off_lw = take(mb.lw.size() * (dev ? sizeof(float) : sizeof(double)));
     } else {
         L.off_fbp = take(9 * row);
         L.off_sg = take(18 * row);
+        L.off_nbr = take((size_t)mb.D * L.np * sizeof(int32_t));
+        L.off_ainv = take(3 * row);
+        L.off_bft = take(std::max<size_t>(1, mb.n_bfaces) * sizeof(int32_t));
     }
     L.off_snap = take(2 * row);
-    L.off_nbr = take((size_t)mb.D * L.np * sizeof(int32_t));
-    L.off_geo = take(6 * (size_t)mb.D * row);
-    L.off_ainv = take(3 * row);
+    L.off_geo = take(6 * (size_t)mb.D * rowf);
     L.off_dtv = take(row);
     L.off_area = take(row);
-    L.off_bft = take(std::max<size_t>(1, mb.n_bfaces) * sizeof(int32_t));
     L.off_bcs = take(std::max<size_t>(1, mb.bcs.size()) * sizeof(DevBC));
     L.off_part = take(4 * kReduceBlocks * sizeof(double));
     L.off_out = take(4 * sizeof(double));
@@ -105,8 +110,11 @@ struct sdugks_s {
         DevState s;
         s.f = at<double>(L.off_f[cur]); s.W = at<double>(L.off_W[cur]); s.G = at<double>(L.off_G[cur]);
         s.fo = at<double>(L.off_f[cur ^ 1]); s.Wo = at<double>(L.off_W[cur ^ 1]); s.Go = at<double>(L.off_G[cur ^ 1]);
+        s.f32 = at<float>(L.off_f[cur]);
+        s.fo32 = at<float>(L.off_f[cur ^ 1]);
         return s;
     }
+    bool dev32() const { return precision == SDUGKS_FP32DEV; }
     DevScratch scratch() const { return {at<double>(L.off_fbp), at<double>(L.off_sg)}; }
 };
 
@@ -120,7 +128,8 @@ namespace {
 int check_prm(const sdugks_params *prm)
 {
     if (!prm) return fail(SDUGKS_EINVAL, "null params");
-    if (prm->precision != SDUGKS_FP64) return fail(SDUGKS_EINVAL, "precision: only SDUGKS_FP64 is built in this library");
+    if (prm->precision != SDUGKS_FP64 && prm->precision != SDUGKS_FP32DEV)
+        return fail(SDUGKS_EINVAL, "precision must be SDUGKS_FP64 or SDUGKS_FP32DEV");
     if (prm->macro_flux != SDUGKS_MACRO_CURRENT && prm->macro_flux != SDUGKS_MACRO_LAGGED)
         return fail(SDUGKS_EINVAL, "macro_flux must be SDUGKS_MACRO_CURRENT or SDUGKS_MACRO_LAGGED");
     if (!(prm->rho0 > 0)) return fail(SDUGKS_EINVAL, "rho0 must be positive");
@@ -136,6 +145,8 @@ int build(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdug
     std::string err;
     rc = build_mesh(mesh, bc, n_bc, prm, mb, err);
     if (rc) return fail(rc, "mesh: " + err);
+    if (prm->precision == SDUGKS_FP32DEV && mb.n_tiles == 0)
+        return fail(SDUGKS_EINVAL, "SDUGKS_FP32DEV needs the fused step (polygons of at most four faces, tile_cells >= 0)");
     return SDUGKS_OK;
 }
 
@@ -182,7 +193,7 @@ int enqueue_step(sdugks_t *h)
 {
     DevState s = h->state();
     if (h->mb.n_tiles > 0) {
-        HIPCHK(launch_step_tiled(h->dm, h->dt, s, h->macro == SDUGKS_MACRO_LAGGED, h->block, h->stream));
+        HIPCHK(launch_step_tiled(h->dm, h->dt, s, h->macro == SDUGKS_MACRO_LAGGED, h->dev32(), h->block, h->stream));
     } else {
         DevScratch x = h->scratch();
         HIPCHK(launch_grad(h->dm, s, x, h->stream));
@@ -240,7 +251,7 @@ int sdugks_state_bytes(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_b
     MeshBuild mb;
     int rc = build(mesh, bc, n_bc, prm, mb);
     if (rc) return rc;
-    *bytes = make_layout(mb).total;
+    *bytes = make_layout(mb, prm->precision).total;
     return SDUGKS_OK;
 }
 
@@ -266,7 +277,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     h->precision = prm->precision;
     h->macro = prm->macro_flux;
     h->rho0 = prm->rho0;
-    h->L = make_layout(h->mb);
+    h->L = make_layout(h->mb, prm->precision);
     const Layout &L = h->L;
     if (workspace) {
         if (workspace_bytes < L.total || ((uintptr_t)workspace % kAlign)) {
@@ -292,17 +303,28 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         return code;
     };
     // geometry
-    rc = upload_rows(h->at<int32_t>(L.off_nbr), mb.nbr, mb.D, nc, np, h->stream);
-    if (rc) return cleanup(rc);
+    const bool dev = h->dev32(), tiled = mb.n_tiles > 0;
     {
         std::vector<double> geo((size_t)6 * mb.D * nc);
         const std::vector<double> *parts[6] = {&mb.lnx, &mb.lny, &mb.rsx, &mb.rsy, &mb.rox, &mb.roy};
         for (int k = 0; k < 6; k++) std::copy(parts[k]->begin(), parts[k]->end(), geo.begin() + (size_t)k * mb.D * nc);
-        rc = upload_rows(h->at<double>(L.off_geo), geo, 6 * (size_t)mb.D, nc, np, h->stream);
+        if (dev) {
+            std::vector<float> g32(geo.begin(), geo.end());
+            rc = upload_rows(h->at<float>(L.off_geo), g32, 6 * (size_t)mb.D, nc, np, h->stream);
+        } else {
+            rc = upload_rows(h->at<double>(L.off_geo), geo, 6 * (size_t)mb.D, nc, np, h->stream);
+        }
         if (rc) return cleanup(rc);
     }
-    rc = upload_rows(h->at<double>(L.off_ainv), mb.ainv, 3, nc, np, h->stream);
-    if (rc) return cleanup(rc);
+    if (!tiled) {
+        rc = upload_rows(h->at<int32_t>(L.off_nbr), mb.nbr, mb.D, nc, np, h->stream);
+        if (rc) return cleanup(rc);
+        rc = upload_rows(h->at<double>(L.off_ainv), mb.ainv, 3, nc, np, h->stream);
+        if (rc) return cleanup(rc);
+        if (mb.n_bfaces &&
+            hipMemcpy(h->at<int32_t>(L.off_bft), mb.bf_tag.data(), mb.n_bfaces * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(SDUGKS_EHIP, "upload of boundary tags failed"));
+    }
     {
         std::vector<double> dtv(nc);
         for (size_t c = 0; c < nc; c++) dtv[c] = mb.dt / mb.area[c];
@@ -311,24 +333,23 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         rc = upload_rows(h->at<double>(L.off_area), mb.area, 1, nc, np, h->stream);
         if (rc) return cleanup(rc);
     }
-    if (mb.n_bfaces) {
-        if (hipMemcpy(h->at<int32_t>(L.off_bft), mb.bf_tag.data(), mb.n_bfaces * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
-            return cleanup(fail(SDUGKS_EHIP, "upload of boundary tags failed"));
-    }
     {
         std::vector<DevBC> bcs(mb.bcs.size());
         for (size_t t = 0; t < bcs.size(); t++) bcs[t] = {mb.bcs[t].type, mb.bcs[t].rho, mb.bcs[t].u, mb.bcs[t].v};
         if (!bcs.empty() && hipMemcpy(h->at<DevBC>(L.off_bcs), bcs.data(), bcs.size() * sizeof(DevBC), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(SDUGKS_EHIP, "upload of the boundary table failed"));
     }
-    if (mb.n_tiles > 0) {
+    if (tiled) {
         auto up = [&](size_t off, const void *src, size_t bytes) {
             return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
         };
+        std::vector<float> lw32;
+        if (dev) lw32.assign(mb.lw.begin(), mb.lw.end());
         if (!up(L.off_thdr, mb.tile_hdr.data(), mb.tile_hdr.size() * sizeof(int32_t)) ||
             !up(L.off_lgid, mb.lgid.data(), mb.lgid.size() * sizeof(int32_t)) ||
             !up(L.off_ladj, mb.ladj.data(), mb.ladj.size() * sizeof(int16_t)) ||
-            !up(L.off_lw, mb.lw.data(), mb.lw.size() * sizeof(double)))
+            !(dev ? up(L.off_lw, lw32.data(), lw32.size() * sizeof(float))
+                  : up(L.off_lw, mb.lw.data(), mb.lw.size() * sizeof(double))))
             return cleanup(fail(SDUGKS_EHIP, "upload of the tile tables failed"));
         h->dt.n_tiles = mb.n_tiles;
         h->dt.nl_max = mb.nl_max;
@@ -336,18 +357,27 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         h->dt.hdr = h->at<int32_t>(L.off_thdr);
         h->dt.lgid = h->at<int32_t>(L.off_lgid);
         h->dt.ladj = h->at<int16_t>(L.off_ladj);
-        h->dt.lw = h->at<double>(L.off_lw);
+        h->dt.lw = dev ? nullptr : h->at<double>(L.off_lw);
+        h->dt.lw32 = dev ? h->at<float>(L.off_lw) : nullptr;
     }
     DevMesh &d = h->dm;
     d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces;
-    d.nbr = h->at<int32_t>(L.off_nbr);
-    const double *geo = h->at<double>(L.off_geo);
     const size_t blk = (size_t)mb.D * np;
-    d.lnx = geo; d.lny = geo + blk; d.rsx = geo + 2 * blk; d.rsy = geo + 3 * blk; d.rox = geo + 4 * blk; d.roy = geo + 5 * blk;
-    d.ainv = h->at<double>(L.off_ainv);
+    if (dev) {
+        const float *g = h->at<float>(L.off_geo);
+        d.lnx32 = g; d.lny32 = g + blk; d.rsx32 = g + 2 * blk; d.rsy32 = g + 3 * blk; d.rox32 = g + 4 * blk; d.roy32 = g + 5 * blk;
+    } else {
+        const double *g = h->at<double>(L.off_geo);
+        d.lnx = g; d.lny = g + blk; d.rsx = g + 2 * blk; d.rsy = g + 3 * blk; d.rox = g + 4 * blk; d.roy = g + 5 * blk;
+    }
+    if (!tiled) {
+        d.nbr = h->at<int32_t>(L.off_nbr);
+        d.ainv = h->at<double>(L.off_ainv);
+        d.bf_tag = h->at<int32_t>(L.off_bft);
+    }
+    d.rho0 = prm->rho0;
     d.dtv = h->at<double>(L.off_dtv);
     d.area = h->at<double>(L.off_area);
-    d.bf_tag = h->at<int32_t>(L.off_bft);
     d.bcs = h->at<DevBC>(L.off_bcs);
     const double tau = mb.tau, dt = mb.dt;
     d.a = (2.0 * tau - dt) / (2.0 * tau);
@@ -388,7 +418,19 @@ int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double
         return SDUGKS_OK;
     };
     int rc;
-    if (f && (rc = put(f, 9, L.off_f[h->cur]))) return rc;
+    if (f && h->dev32()) {
+        // deviation form: store f - w_i rho0 in FP32
+        static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        std::vector<float> b32(9 * np, 0.0f);
+        for (size_t k = 0; k < nc; k++) {
+            size_t c = h->mb.perm[k];
+            for (int i = 0; i < 9; i++) b32[i * np + k] = (float)(f[c * 9 + i] - w[i] * h->rho0);
+        }
+        HIPCHK(hipMemcpyAsync(h->base + L.off_f[h->cur], b32.data(), 9 * np * sizeof(float), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+    } else if (f && (rc = put(f, 9, L.off_f[h->cur]))) {
+        return rc;
+    }
     if (W) {
         if ((rc = put(W, 3, L.off_W[h->cur]))) return rc;
         // snapshot of the residual = this velocity field
@@ -424,7 +466,18 @@ int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G)
         return SDUGKS_OK;
     };
     int rc;
-    if (f && (rc = get(f, 9, L.off_f[h->cur]))) return rc;
+    if (f && h->dev32()) {
+        static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        std::vector<float> b32(9 * np);
+        HIPCHK(hipMemcpyAsync(b32.data(), h->base + L.off_f[h->cur], 9 * np * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (size_t k = 0; k < nc; k++) {
+            size_t c = h->mb.perm[k];
+            for (int i = 0; i < 9; i++) f[c * 9 + i] = w[i] * h->rho0 + (double)b32[i * np + k];
+        }
+    } else if (f && (rc = get(f, 9, L.off_f[h->cur]))) {
+        return rc;
+    }
     if (W && (rc = get(W, 3, L.off_W[h->cur]))) return rc;
     if (G) {
         if (h->macro == SDUGKS_MACRO_LAGGED) { if ((rc = get(G, 3, L.off_G[h->cur]))) return rc; }
@@ -476,7 +529,7 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
         const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
         HIPCHK(hipEventRecord(ev[0], h->stream));
         if (tiled) {
-            HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->block, h->stream));
+            HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->dev32(), h->block, h->stream));
             HIPCHK(hipEventRecord(ev[1], h->stream));
         } else {
             DevScratch x = h->scratch();
@@ -550,8 +603,9 @@ int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i)
 {
     if (!h || cell < 0 || cell >= h->mb.nc || i < 0 || i > 8) return fail(SDUGKS_EINVAL, "bad poison target");
     HIPCHK(hipSetDevice(h->device));
-    double *p = h->at<double>(h->L.off_f[h->cur]) + (size_t)i * h->L.np + h->mb.iperm[cell];
-    HIPCHK(launch_poke(p, NAN, h->stream));
+    const size_t idx = (size_t)i * h->L.np + h->mb.iperm[cell];
+    void *p = h->dev32() ? (void *)(h->at<float>(h->L.off_f[h->cur]) + idx) : (void *)(h->at<double>(h->L.off_f[h->cur]) + idx);
+    HIPCHK(launch_poke_nan(p, h->dev32() ? 4 : 8, h->stream));
     return sync_check(h);
 }
 

@@ -26,12 +26,18 @@ struct DevMesh {
     const int32_t *bf_tag;              // [n_bfaces]
     const DevBC *bcs;                   // [n_bc]
     double a, b, c1, lam, dt;           // (2tau-dt)/2tau, dt/2tau, 2tau/(2tau+dt), dt/tau, dt
+    // FP32 copies of the face geometry for the deviation form (null otherwise)
+    const float *lnx32, *lny32, *rsx32, *rsy32, *rox32, *roy32;
+    double rho0;                        // offset of the deviation form: f = w_i rho0 + stored value
 };
 
-// FP64 state buffers of one step: read (in) and write (out).
+// State buffers of one step: read (in) and write (out).  f is FP64 ([9][np]
+// doubles) or, in the deviation form, f - w_i rho0 in FP32 (f32 / fo32).
 struct DevState {
     const double *f, *W, *G;            // [9][np], [3][np], [3][np]
     double *fo, *Wo, *Go;
+    const float *f32;
+    float *fo32;
 };
 
 // Tiles of the fused step (see MeshBuild): headers [n_tiles][8] (g0, nt, n1,
@@ -42,7 +48,8 @@ struct DevTiles {
     const int32_t *hdr;
     const int32_t *lgid;
     const int16_t *ladj;
-    const double *lw;
+    const double *lw;                   // FP64 form
+    const float *lw32;                  // deviation form
 };
 
 struct DevScratch {
@@ -54,16 +61,16 @@ struct DevScratch {
 hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st);
 hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st);
 // Fused one-kernel step over tiles (D <= 4 slots per cell).
-hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int block,
-                             hipStream_t st);
-size_t step_tiled_lds_bytes(const DevTiles &t);
+hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
+                             int block, hipStream_t st);
+size_t step_tiled_lds_bytes(const DevTiles &t, int dev32);
 // Deterministic reductions of the residual / mass / finiteness check: writes
 // out4 = {sum |u-u_snap|^2, sum |u_snap|^2, sum V rho, count of non-finite}.
 // snap = [2][np] (U, V); update_snap re-snapshots.
 hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int update_snap, double *partials,
                          double *out4, hipStream_t st);
-// f[i][c] = value (failure injection).
-hipError_t launch_poke(double *p, double value, hipStream_t st);
+// *p = NaN, p pointing at a double (bytes 8) or a float (bytes 4): failure injection.
+hipError_t launch_poke_nan(void *p, int bytes, hipStream_t st);
 
 constexpr int kReduceBlocks = 256;
 constexpr int kXcds = 8;           // accelerator complex dies of an MI355X, each with its own L2

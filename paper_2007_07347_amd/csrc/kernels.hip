@@ -226,7 +226,11 @@ __global__ void __launch_bounds__(256) k_reduce_final(const double *partials, do
     if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_poke(double *p, double v) { *p = v; }
+__global__ void k_poke_nan(void *p, int bytes)
+{
+    if (bytes == 8) *reinterpret_cast<double *>(p) = __builtin_nan("");
+    else *reinterpret_cast<float *>(p) = __builtin_nanf("");
+}
 
 }  // namespace
 
@@ -259,9 +263,9 @@ hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int up
     return hipGetLastError();
 }
 
-hipError_t launch_poke(double *p, double value, hipStream_t st)
+hipError_t launch_poke_nan(void *p, int bytes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_poke, dim3(1), dim3(1), 0, st, p, value);
+    hipLaunchKernelGGL(k_poke_nan, dim3(1), dim3(1), 0, st, p, bytes);
     return hipGetLastError();
 }
 

@@ -15,12 +15,21 @@
 //            fixed order; then W^{n+1} (Eq. MacroUpdate), feq^{n+1} and
 //            f^{n+1} (Eq. fn+1), each lane writing two or three velocities.
 //
+// Two storage forms share the code: FP64 f, or (DEV) the deviation
+// f - w_i rho0 in FP32 with FP32 face geometry, gradients and face fluxes
+// computed on deviations (the constant parts cancel exactly: sum_i w_i e_i = 0
+// and the scaled normals of a closed cell sum to zero), per-cell flux sums
+// compensated (TwoSum), and W, its update, feq and the macroscopic fluxes in
+// FP64.
+//
 // Every global input of phases 2 and 3 (weights, adjacency, face geometry,
 // the old f of the lane's velocities) is requested at kernel start, so its
 // latency overlaps phase 1.  Each XCD sweeps a contiguous range of bisection
 // tiles, so the halo cells a tile reads are mostly L2 hits.  A face shared by
 // two tiles is evaluated by both from identical operands: the flux that
 // leaves one cell enters the other exactly.
+#include <type_traits>
+
 #include "d2q9.h"
 #include "device.h"
 
@@ -33,6 +42,24 @@ __device__ __forceinline__ double lane_sum4(double v)
     v += __shfl_xor(v, 1, 64);
     v += __shfl_xor(v, 2, 64);
     return v;
+}
+
+// Compensated sum over the four lanes of a cell: TwoSum at each butterfly
+// level (its error term is exact whatever the operand order, so every lane
+// ends with the same bits), errors added at the end.
+__device__ __forceinline__ float lane_sum4_comp(float v)
+{
+    float e = 0.0f;
+#pragma unroll
+    for (int off = 1; off < 4; off <<= 1) {
+        const float b = __shfl_xor(v, off, 64), eb = __shfl_xor(e, off, 64);
+        const float sum = v + b;
+        const float bb = sum - v;
+        const float err = (v - (sum - bb)) + (b - bb);
+        e = (e + eb) + err;
+        v = sum;
+    }
+    return v + e;
 }
 
 __device__ __forceinline__ void boundary_state_t(const DevBC &bc, double rho, double ux, double uy,
@@ -48,9 +75,10 @@ __device__ __forceinline__ double ex_rt(int i) { return (double)((0x20919 >> (2 
 __device__ __forceinline__ double ey_rt(int i) { return (double)((0x02865 >> (2 * i) & 3) - 1); }
 __device__ __forceinline__ double w_rt(int i) { return i == 0 ? 4.0 / 9 : (i < 5 ? 1.0 / 9 : 1.0 / 36); }
 
-template <int D>
+template <int D, bool DEV>
 __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevState s, int lagged)
 {
+    using R = typename std::conditional<DEV, float, double>::type;   // storage / face arithmetic
     extern __shared__ double smem[];
     // Workgroups are dealt round-robin to the XCDs; give XCD x the contiguous
     // tile range [x * per, (x + 1) * per).
@@ -62,47 +90,67 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
     const int P = tl.nl_max, P1 = tl.na_max;
     const int np = m.np;
     const int tid = threadIdx.x;
-    double *sfbp = smem;               // [9][P]
-    double *sW = smem + 9 * P;         // [5][P]: rho, rho u, rho v, u, v
-    double *ssg = smem + 14 * P;       // [18][P1] gradient (x rows 0..8, y rows 9..17)
+    double *sW = smem;                                        // [5][P]: rho, rho u, rho v, u, v
+    R *sfbp = reinterpret_cast<R *>(smem + 5 * P);            // [9][P] fbar+ (deviation in DEV)
+    R *ssg = sfbp + 9 * P;                                    // [18][P1] gradient (x rows 0..8, y rows 9..17)
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
-    const double *lw = tl.lw + (size_t)t * D * 2 * P1;
+    const R *lw;
+    const R *glnx, *glny, *grsx, *grsy, *grox, *groy;
+    if constexpr (DEV) {
+        lw = tl.lw32 + (size_t)t * D * 2 * P1;
+        glnx = m.lnx32; glny = m.lny32; grsx = m.rsx32; grsy = m.rsy32; grox = m.rox32; groy = m.roy32;
+    } else {
+        lw = tl.lw + (size_t)t * D * 2 * P1;
+        glnx = m.lnx; glny = m.lny; grsx = m.rsx; grsy = m.rsy; grox = m.rox; groy = m.roy;
+    }
+    const R ra = (R)m.a, rb_ = (R)m.b, rc1 = (R)m.c1, rdt = (R)m.dt;
+    // constant part of f removed in the deviation form
+    auto off = [&](int i) { return DEV ? kW[i] * m.rho0 : 0.0; };
 
     // ---- requests of all phases
     const bool p1 = tid < nl;
     const int g1 = p1 ? tl.lgid[(size_t)t * P + tid] : 0;
     const bool p2 = tid < na;
     int la2[D];
-    double wx2[D], wy2[D];
+    R wx2[D], wy2[D];
 #pragma unroll
     for (int sl = 0; sl < D; sl++) {
         la2[sl] = p2 ? ladj[sl * P1 + tid] : -1;
-        wx2[sl] = p2 ? lw[(2 * sl) * P1 + tid] : 0.0;
-        wy2[sl] = p2 ? lw[(2 * sl + 1) * P1 + tid] : 0.0;
+        wx2[sl] = p2 ? lw[(2 * sl) * P1 + tid] : (R)0;
+        wy2[sl] = p2 ? lw[(2 * sl + 1) * P1 + tid] : (R)0;
     }
     const int lc3 = tid >> 2, sl3 = tid & 3;
     const bool p3 = lc3 < nt;
     const int g3 = g0 + lc3;
     const int la3 = (p3 && sl3 < D) ? ladj[sl3 * P1 + lc3] : -1;
     const int q3 = sl3 * np + g3;
-    double lnx = 0.0, lny = 0.0, rsx = 0.0, rsy = 0.0, rox = 0.0, roy = 0.0;
-    if (la3 != -1) { lnx = m.lnx[q3]; lny = m.lny[q3]; rsx = m.rsx[q3]; rsy = m.rsy[q3]; }
-    if (la3 >= 0) { rox = m.rox[q3]; roy = m.roy[q3]; }
+    R lnx = 0, lny = 0, rsx = 0, rsy = 0, rox = 0, roy = 0;
+    if (la3 != -1) { lnx = glnx[q3]; lny = glny[q3]; rsx = grsx[q3]; rsy = grsy[q3]; }
+    if (la3 >= 0) { rox = grox[q3]; roy = groy[q3]; }
     // the lane's velocities in the update: sl3, sl3 + 4 and, on lane 0, 8
     double fo0 = 0.0, fo1 = 0.0, fo2 = 0.0, dtv = 0.0;
     if (p3) {
-        fo0 = s.f[(size_t)sl3 * np + g3];
-        fo1 = s.f[(size_t)(sl3 + 4) * np + g3];
-        if (sl3 == 0) fo2 = s.f[(size_t)8 * np + g3];
+        if constexpr (DEV) {
+            fo0 = s.f32[(size_t)sl3 * np + g3];
+            fo1 = s.f32[(size_t)(sl3 + 4) * np + g3];
+            if (sl3 == 0) fo2 = s.f32[(size_t)8 * np + g3];
+        } else {
+            fo0 = s.f[(size_t)sl3 * np + g3];
+            fo1 = s.f[(size_t)(sl3 + 4) * np + g3];
+            if (sl3 == 0) fo2 = s.f[(size_t)8 * np + g3];
+        }
         dtv = m.dtv[g3];
     }
 
     // ---- phase 1: macros and fbar+ of every local cell
     if (p1) {
         const double r = s.W[g1], mu = s.W[np + g1], mv = s.W[2 * np + g1];
-        double fv[9];
+        R fv[9];
 #pragma unroll
-        for (int i = 0; i < 9; i++) fv[i] = s.f[(size_t)i * np + g1];
+        for (int i = 0; i < 9; i++) {
+            if constexpr (DEV) fv[i] = s.f32[(size_t)i * np + g1];
+            else fv[i] = s.f[(size_t)i * np + g1];
+        }
         const double ux = mu / r, uy = mv / r;
         sW[tid] = r;
         sW[P + tid] = mu;
@@ -110,15 +158,16 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
         sW[3 * P + tid] = ux;
         sW[4 * P + tid] = uy;
 #pragma unroll
-        for (int i = 0; i < 9; i++) sfbp[i * P + tid] = m.a * fv[i] + m.b * feq_one(kW[i], kEx[i], kEy[i], r, ux, uy);
+        for (int i = 0; i < 9; i++)
+            sfbp[i * P + tid] = ra * fv[i] + rb_ * (R)(feq_one(kW[i], kEx[i], kEy[i], r, ux, uy) - off(i));
     }
     __syncthreads();
 
     // ---- phase 2: gradients of the tile and its first ring
     if (p2) {
-        double ax[9], ay[9], fc[9];
+        R ax[9], ay[9], fc[9];
 #pragma unroll
-        for (int i = 0; i < 9; i++) { ax[i] = 0.0; ay[i] = 0.0; fc[i] = sfbp[i * P + tid]; }
+        for (int i = 0; i < 9; i++) { ax[i] = 0; ay[i] = 0; fc[i] = sfbp[i * P + tid]; }
 #pragma unroll
         for (int sl = 0; sl < D; sl++) {
             const int la = la2[sl];
@@ -126,7 +175,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
             if (la >= 0) {
 #pragma unroll
                 for (int i = 0; i < 9; i++) {
-                    const double df = sfbp[i * P + la] - fc[i];
+                    const R df = sfbp[i * P + la] - fc[i];
                     ax[i] += wx2[sl] * df;
                     ay[i] += wy2[sl] * df;
                 }
@@ -138,7 +187,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
                 boundary_state_t(bc, r, ux, uy, rb, ub, vb);
 #pragma unroll
                 for (int i = 0; i < 9; i++) {
-                    const double df = feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy);
+                    const R df = (R)(feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy));
                     ax[i] += wx2[sl] * df;
                     ay[i] += wy2[sl] * df;
                 }
@@ -153,22 +202,24 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
     __syncthreads();
 
     // ---- phase 3: the face of each lane, per-cell sums, update
-    double phi[9], g0s = 0.0, g1s = 0.0, g2s = 0.0;
+    R phi[9];
+    double g0s = 0.0, g1s = 0.0, g2s = 0.0;
 #pragma unroll
-    for (int i = 0; i < 9; i++) phi[i] = 0.0;
+    for (int i = 0; i < 9; i++) phi[i] = 0;
     if (la3 != -1) {
         const int lc = lc3;
-        double fbar[9];
+        R fbar[9];
         if (la3 >= 0) {
             const int la = la3;
 #pragma unroll
             for (int i = 0; i < 9; i++) {
-                const double sn = kEx[i] * lnx + kEy[i] * lny;
-                const double rs = sfbp[i * P + lc] + (rsx - m.dt * kEx[i]) * ssg[i * P1 + lc]
-                                  + (rsy - m.dt * kEy[i]) * ssg[(9 + i) * P1 + lc];
-                const double ro = sfbp[i * P + la] + (rox - m.dt * kEx[i]) * ssg[i * P1 + la]
-                                  + (roy - m.dt * kEy[i]) * ssg[(9 + i) * P1 + la];
-                fbar[i] = sn > 0.0 ? rs : (sn < 0.0 ? ro : 0.5 * (rs + ro));
+                const R ex = (R)kEx[i], ey = (R)kEy[i];
+                const R sn = ex * lnx + ey * lny;
+                const R rs = sfbp[i * P + lc] + (rsx - rdt * ex) * ssg[i * P1 + lc]
+                             + (rsy - rdt * ey) * ssg[(9 + i) * P1 + lc];
+                const R ro = sfbp[i * P + la] + (rox - rdt * ex) * ssg[i * P1 + la]
+                             + (roy - rdt * ey) * ssg[(9 + i) * P1 + la];
+                fbar[i] = sn > (R)0 ? rs : (sn < (R)0 ? ro : (R)0.5 * (rs + ro));
             }
         } else {
             const DevBC bc = m.bcs[-2 - la3];
@@ -177,31 +228,45 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
             boundary_state_t(bc, r, ux, uy, rb, ub, vb);
 #pragma unroll
             for (int i = 0; i < 9; i++) {
-                const double sn = kEx[i] * lnx + kEy[i] * lny;
-                const double sx = ssg[i * P1 + lc], sy = ssg[(9 + i) * P1 + lc];
-                const double fb = sfbp[i * P + lc];
-                const double inner = fb + (rsx - m.dt * kEx[i]) * sx + (rsy - m.dt * kEy[i]) * sy;
+                const R ex = (R)kEx[i], ey = (R)kEy[i];
+                const R sn = ex * lnx + ey * lny;
+                const R sx = ssg[i * P1 + lc], sy = ssg[(9 + i) * P1 + lc];
+                const R fb = sfbp[i * P + lc];
+                const R inner = fb + (rsx - rdt * ex) * sx + (rsy - rdt * ey) * sy;
                 // incoming: the boundary state's fbar+ carried to the foot point
-                const double gb = feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) + fb
-                                  - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy);
-                fbar[i] = sn >= 0.0 ? inner : gb - m.dt * (kEx[i] * sx + kEy[i] * sy);
+                const R gb = (R)(feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy)) + fb;
+                fbar[i] = sn >= (R)0 ? inner : gb - rdt * (ex * sx + ey * sy);
             }
         }
-        double rf = 0.0, mx = 0.0, my = 0.0;
+        // face macros (deviations in DEV: rho_f = rho0 + sum, momentum unchanged)
+        R rsum = 0, mx = 0, my = 0;
 #pragma unroll
-        for (int i = 0; i < 9; i++) { rf += fbar[i]; mx += kEx[i] * fbar[i]; my += kEy[i] * fbar[i]; }
-        const double uf = mx / rf, vf = my / rf;
+        for (int i = 0; i < 9; i++) { rsum += fbar[i]; mx += (R)kEx[i] * fbar[i]; my += (R)kEy[i] * fbar[i]; }
+        const R rf = DEV ? (R)m.rho0 + rsum : rsum;
+        const R uf = mx / rf, vf = my / rf;
+        const R uu = uf * uf + vf * vf;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
-            const double sn = kEx[i] * lnx + kEy[i] * lny;
-            phi[i] = sn * (m.c1 * (fbar[i] + m.b * feq_one(kW[i], kEx[i], kEy[i], rf, uf, vf)));
-            g0s += phi[i];
-            g1s += kEx[i] * phi[i];
-            g2s += kEy[i] * phi[i];
+            const R ex = (R)kEx[i], ey = (R)kEy[i];
+            const R sn = ex * lnx + ey * lny;
+            R fe;
+            if constexpr (DEV) {
+                const R eu = ex * uf + ey * vf;
+                fe = (R)kW[i] * (rsum + rf * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * uu));
+            } else {
+                fe = feq_one(kW[i], kEx[i], kEy[i], rf, uf, vf);
+            }
+            phi[i] = sn * (rc1 * (fbar[i] + rb_ * fe));
+            g0s += (double)phi[i];
+            g1s += kEx[i] * (double)phi[i];
+            g2s += kEy[i] * (double)phi[i];
         }
     }
 #pragma unroll
-    for (int i = 0; i < 9; i++) phi[i] = lane_sum4(phi[i]);
+    for (int i = 0; i < 9; i++) {
+        if constexpr (DEV) phi[i] = lane_sum4_comp(phi[i]);
+        else phi[i] = lane_sum4(phi[i]);
+    }
     g0s = lane_sum4(g0s);
     g1s = lane_sum4(g1s);
     g2s = lane_sum4(g2s);
@@ -226,31 +291,43 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
         const int i0 = sl3, i1 = sl3 + 4;
         const double F0 = sl3 == 0 ? phi[0] : (sl3 == 1 ? phi[1] : (sl3 == 2 ? phi[2] : phi[3]));
         const double F1 = sl3 == 0 ? phi[4] : (sl3 == 1 ? phi[5] : (sl3 == 2 ? phi[6] : phi[7]));
-        const double fe0 = feq_one(w_rt(i0), ex_rt(i0), ey_rt(i0), rn, un, vn);
-        const double fe1 = feq_one(w_rt(i1), ex_rt(i1), ey_rt(i1), rn, un, vn);
-        s.fo[(size_t)i0 * np + g] = (fo0 - dtv * F0 + m.lam * fe0) * inv;
-        s.fo[(size_t)i1 * np + g] = (fo1 - dtv * F1 + m.lam * fe1) * inv;
+        const double o0 = DEV ? w_rt(i0) * m.rho0 : 0.0, o1 = DEV ? w_rt(i1) * m.rho0 : 0.0;
+        const double fe0 = feq_one(w_rt(i0), ex_rt(i0), ey_rt(i0), rn, un, vn) - o0;
+        const double fe1 = feq_one(w_rt(i1), ex_rt(i1), ey_rt(i1), rn, un, vn) - o1;
+        const double v0 = (fo0 - dtv * F0 + m.lam * fe0) * inv, v1 = (fo1 - dtv * F1 + m.lam * fe1) * inv;
+        if constexpr (DEV) { s.fo32[(size_t)i0 * np + g] = (float)v0; s.fo32[(size_t)i1 * np + g] = (float)v1; }
+        else { s.fo[(size_t)i0 * np + g] = v0; s.fo[(size_t)i1 * np + g] = v1; }
         if (sl3 == 0) {
-            const double fe2 = feq_one(kW[8], kEx[8], kEy[8], rn, un, vn);
-            s.fo[(size_t)8 * np + g] = (fo2 - dtv * phi[8] + m.lam * fe2) * inv;
+            const double fe2 = feq_one(kW[8], kEx[8], kEy[8], rn, un, vn) - off(8);
+            const double v2 = (fo2 - dtv * (double)phi[8] + m.lam * fe2) * inv;
+            if constexpr (DEV) s.fo32[(size_t)8 * np + g] = (float)v2;
+            else s.fo[(size_t)8 * np + g] = v2;
         }
     }
 }
 
 }  // namespace
 
-size_t step_tiled_lds_bytes(const DevTiles &t) { return (14 * (size_t)t.nl_max + 18 * (size_t)t.na_max) * sizeof(double); }
+size_t step_tiled_lds_bytes(const DevTiles &t, int dev32)
+{
+    const size_t r = dev32 ? sizeof(float) : sizeof(double);
+    return 5 * (size_t)t.nl_max * sizeof(double) + (9 * (size_t)t.nl_max + 18 * (size_t)t.na_max) * r;
+}
 
 static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)((t.n_tiles + kXcds - 1) / kXcds * kXcds); }
 
-hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int block,
-                             hipStream_t st)
+hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
+                             int block, hipStream_t st)
 {
-    const size_t lds = step_tiled_lds_bytes(t);
-    if (m.D <= 3)
-        hipLaunchKernelGGL(k_step_tiled<3>, dim3(step_tiled_grid(t)), dim3(block), lds, st, m, t, s, lagged);
-    else
-        hipLaunchKernelGGL(k_step_tiled<4>, dim3(step_tiled_grid(t)), dim3(block), lds, st, m, t, s, lagged);
+    const size_t lds = step_tiled_lds_bytes(t, dev32);
+    const dim3 grid(step_tiled_grid(t)), blk(block);
+    if (m.D <= 3) {
+        if (dev32) hipLaunchKernelGGL((k_step_tiled<3, true>), grid, blk, lds, st, m, t, s, lagged);
+        else hipLaunchKernelGGL((k_step_tiled<3, false>), grid, blk, lds, st, m, t, s, lagged);
+    } else {
+        if (dev32) hipLaunchKernelGGL((k_step_tiled<4, true>), grid, blk, lds, st, m, t, s, lagged);
+        else hipLaunchKernelGGL((k_step_tiled<4, false>), grid, blk, lds, st, m, t, s, lagged);
+    }
     return hipGetLastError();
 }
 

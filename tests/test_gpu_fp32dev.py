@@ -1,0 +1,129 @@
+"""FP32-deviation storage form on the GPU: f stored as f - w_i rho0 in FP32
+(face geometry, gradients and face fluxes in FP32 on deviations, compensated
+per-cell flux sums), W, its update, mass and residual in FP64.
+
+Bars: short generic-state windows stay within 2e-6 relative of the FP64
+oracle (single rounding is 6e-8 on values of order 0.1, a few hundred
+operations per step); converged velocities stay within 1e-5 relative L2 of
+the FP64 GPU solution, which is itself parity-checked against the oracle;
+mass is conserved to FP64 rounding on closed domains (face mass fluxes are
+formed in FP64 from bit-identical face evaluations).
+"""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_07347_amd import sdugks
+    return sdugks
+
+
+def rel_linf(x, y):
+    return np.abs(x - y).max() / np.abs(y).max()
+
+
+CASES = {
+    "cavity_23": (lambda: meshgen.cavity(23), dict(nu=0.001, cfl=0.5)),
+    "ogrid_37x11": (lambda: meshgen.cylinder_ogrid(37, 11, seed=4), dict(nu=0.0025, cfl=0.5, u0=0.1)),
+    "periodic_tri_9": (lambda: meshgen.jittered_periodic_triangles(9, seed=6), dict(nu=0.004, cfl=0.5)),
+    "inlet_outlet_13x9": (lambda: meshgen.inlet_outlet_box(13, 9), dict(nu=0.005, cfl=0.5)),
+    "couette_5x16": (lambda: meshgen.couette(5, 16), dict(nu=0.01, cfl=0.5)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_window_against_fp64_oracle(sd, oracle_mod, name):
+    build, kw = CASES[name]
+    mesh, bcs = build()
+    o = oracle_mod.Oracle(mesh, bcs, **kw)
+    g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, **kw)
+    f, W, _ = meshgen.random_state(o.n_cells, seed=23, amp=0.02)
+    o.set_state(f, W)
+    g.set_state(f, W)
+    o.step(40)
+    g.step(40)
+    fg, Wg, _ = g.state()
+    fo, Wo, _ = o.state()
+    ef, er, em = rel_linf(fg, fo), rel_linf(Wg[:, 0], Wo[:, 0]), rel_linf(Wg[:, 1:], Wo[:, 1:])
+    print(name, f"f {ef:.2e} rho {er:.2e} mom {em:.2e}", flush=True)
+    assert ef <= 2e-6 and er <= 2e-6 and em <= 2e-6
+
+
+def test_couette_profile(sd):
+    mesh, bcs = meshgen.couette(4, 32, 0.1)
+    g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, nu=0.01, cfl=0.5)
+    y = sd.geometry(mesh, bcs, nu=0.01)["cy"]
+    eps = 1.0
+    for _ in range(60):
+        g.step(1000)
+        eps = g.residual()
+        if eps < 1e-9:
+            break
+    _, u, v = g.macros()
+    print("couette fp32dev eps", eps, "max |u - U y|", np.abs(u - 0.1 * y).max(), flush=True)
+    assert np.abs(u - 0.1 * y).max() <= 1e-7 and np.abs(v).max() <= 1e-8
+
+
+def test_converged_cavity_velocity_l2(sd):
+    """Lid-driven cavity, 48 x 48 tanh mesh (the paper's resolution), Re = 400:
+    FP64 run to residual 1e-8, the deviation form run the same number of steps.
+    FP32 rounding of the stored deviations leaves a residual floor of a few
+    1e-8 (below the 1e-7 tolerance of the serving loop, above 1e-8), so the
+    comparison is made at equal step counts."""
+    mesh, bcs = meshgen.cavity(48)
+    kw = dict(nu=0.1 / 400, cfl=0.5)
+    g64 = sd.Solver(mesh, bcs, precision=sd.FP64, **kw)
+    g32 = sd.Solver(mesh, bcs, precision=sd.FP32DEV, **kw)
+    m64, m32 = g64.mass(), g32.mass()
+    eps64, steps = 1.0, 0
+    while eps64 > 1e-8 and steps < 400_000:
+        g64.step(1000)
+        g32.step(1000)
+        steps += 1000
+        eps64 = g64.residual()
+        eps32 = g32.residual()
+    _, u64, v64 = g64.macros()
+    _, u32, v32 = g32.macros()
+    l2 = np.sqrt(((u32 - u64) ** 2 + (v32 - v64) ** 2).sum() / (u64 ** 2 + v64 ** 2).sum())
+    linf = max(np.abs(u32 - u64).max(), np.abs(v32 - v64).max()) / max(np.abs(u64).max(), np.abs(v64).max())
+    drift64 = (g64.mass() - m64) / m64
+    drift32 = (g32.mass() - m32) / m32
+    print(f"cavity48 Re400 after {steps} steps: residual fp64 {eps64:.2e} fp32dev {eps32:.2e}; "
+          f"velocity L2 {l2:.2e} Linf {linf:.2e}; mass drift fp64 {drift64:.4e} fp32dev {drift32:.4e}", flush=True)
+    assert eps64 <= 1e-8 and eps32 <= 1e-7
+    assert l2 <= 1e-5 and linf <= 1e-5
+    assert abs(drift32 - drift64) <= 1e-6
+
+
+def test_mass_conserved_periodic(sd):
+    mesh, bcs = meshgen.jittered_periodic_triangles(24, seed=8)
+    g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, nu=0.004, cfl=0.5)
+    f, W, _ = meshgen.random_state(g.n_cells, seed=5, amp=0.02)
+    g.set_state(f, W)
+    m0 = g.mass()
+    g.step(2000)
+    assert abs(g.mass() - m0) / m0 <= 1e-13
+
+
+def test_deterministic(sd):
+    mesh, bcs = meshgen.cylinder_ogrid(64, 20, seed=2)
+    runs = []
+    for _ in range(2):
+        g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, nu=0.002, cfl=0.5, u0=0.1)
+        g.step(300)
+        runs.append(g.state())
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
+def test_two_kernel_step_rejects_fp32dev(sd):
+    with pytest.raises(sd.SdugksError) as ei:
+        sd.Solver(*meshgen.hexagon_strip(4, 3), precision=sd.FP32DEV, nu=0.01)
+    assert ei.value.code == sd.EINVAL
