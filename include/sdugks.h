@@ -167,11 +167,26 @@ int sdugks_destroy(sdugks_t *h);
 
 const char *sdugks_last_error(void);
 
-/* ---- batched form: many independent instances advanced by one launch per step.
- * Members keep their own state and must share precision and macro mode; they
- * stay usable individually.  The batch does not own them. */
+/* ---- batched form: many independent instances (uneven meshes, their own tau,
+ * dt and boundary tables) advanced by one launch per step over the tiles of
+ * all members; members with three-slot and four-slot cells, or with the two
+ * storage forms, go to separate launches.  Each XCD sweeps a contiguous range
+ * of the concatenated tile sequence.  Steps are replayed from a captured
+ * two-step hipGraph that reads a device-side member table, so changing the
+ * membership only rewrites the table unless the tile count outgrows the
+ * launch capacity (it is then re-captured).
+ *  - members: handles using the fused step (n >= 1, no duplicates, same
+ *    device); they keep their own state and stay usable individually, and the
+ *    batch does not own them: destroy the batch (or change its membership)
+ *    before destroying a member.
+ *  - stream: a hipStream_t that is not the null stream, or NULL for the batch
+ *    to create its own; the batch orders itself after each member's stream
+ *    before stepping and each member's stream after itself afterwards.
+ * Results are bitwise those of stepping each member alone. */
 typedef struct sdugks_batch_s sdugks_batch_t;
 int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugks_batch_t **out);
+/* Replace the membership (continuous batching): waits for the batch stream. */
+int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_t n);
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n);
 int sdugks_batch_destroy(sdugks_batch_t *b);
 

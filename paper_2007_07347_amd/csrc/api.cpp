@@ -118,9 +118,27 @@ struct sdugks_s {
     DevScratch scratch() const { return {at<double>(L.off_fbp), at<double>(L.off_sg)}; }
 };
 
+// Members of one launch: same face class (three or four slots) and storage.
+struct BatchGroup {
+    int D = 4, dev32 = 0, block = 64;
+    size_t lds = 0;
+    int n_inst = 0, n_tiles = 0, cap_inst = 0, cap_tiles = 0;
+    BatchInst *d_inst = nullptr;      // device table, capacity cap_inst
+    int32_t *d_begin = nullptr;       // cap_inst + 1
+    int32_t *d_count = nullptr;       // 2
+    std::vector<int> members;         // indices into the batch's member list
+};
+
 struct sdugks_batch_s {
     std::vector<sdugks_t *> members;
+    std::vector<BatchGroup> groups;
     hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+    std::vector<int> cur_at_fill;     // members' buffer indices when the tables were filled
 };
 
 namespace {
@@ -609,30 +627,241 @@ int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i)
     return sync_check(h);
 }
 
+namespace {
+
+size_t next_pow2(size_t x)
+{
+    size_t p = 8;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+void batch_release_graph(sdugks_batch_t *b)
+{
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+void batch_release_groups(sdugks_batch_t *b)
+{
+    for (auto &g : b->groups) {
+        hipFree(g.d_inst);
+        hipFree(g.d_begin);
+        hipFree(g.d_count);
+    }
+    b->groups.clear();
+}
+
+// (Re)build the device tables for the current members.  Existing tables and
+// the captured graph are kept when every group still fits their capacity,
+// launch shape and LDS; otherwise they are reallocated and the graph dropped.
+int batch_build(sdugks_batch_t *b)
+{
+    std::vector<BatchGroup> want;
+    for (size_t k = 0; k < b->members.size(); k++) {
+        sdugks_t *h = b->members[k];
+        const int D = h->mb.D <= 3 ? 3 : 4, dev = h->dev32();
+        BatchGroup *g = nullptr;
+        for (auto &x : want) if (x.D == D && x.dev32 == dev) g = &x;
+        if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->dev32 = dev; }
+        g->members.push_back((int)k);
+        g->block = std::max(g->block, h->block);
+        g->lds = std::max(g->lds, step_tiled_lds_bytes(h->dt, dev));
+        g->n_inst++;
+        g->n_tiles += h->mb.n_tiles;
+    }
+    bool reuse = want.size() == b->groups.size();
+    for (size_t k = 0; reuse && k < want.size(); k++) {
+        const BatchGroup &o = b->groups[k], &n = want[k];
+        reuse = o.D == n.D && o.dev32 == n.dev32 && o.block >= n.block && o.lds >= n.lds &&
+                o.cap_inst >= n.n_inst && o.cap_tiles >= n.n_tiles;
+    }
+    if (!reuse) {
+        batch_release_graph(b);
+        batch_release_groups(b);
+        for (auto &g : want) {
+            g.cap_inst = (int)next_pow2(g.n_inst);
+            g.cap_tiles = (int)next_pow2(g.n_tiles);
+            g.lds = std::min(g.lds + g.lds / 4, kTileLdsLimit);    // headroom for later members
+            if (hipMalloc((void **)&g.d_inst, g.cap_inst * sizeof(BatchInst)) != hipSuccess ||
+                hipMalloc((void **)&g.d_begin, (g.cap_inst + 1) * sizeof(int32_t)) != hipSuccess ||
+                hipMalloc((void **)&g.d_count, 2 * sizeof(int32_t)) != hipSuccess)
+                return fail(SDUGKS_ENOMEM, "hipMalloc of a batch table failed");
+        }
+        b->groups = want;
+        for (auto &g : want) g.d_inst = nullptr, g.d_begin = nullptr, g.d_count = nullptr;
+    } else {
+        for (size_t k = 0; k < want.size(); k++) {
+            b->groups[k].members = want[k].members;
+            b->groups[k].n_inst = want[k].n_inst;
+            b->groups[k].n_tiles = want[k].n_tiles;
+        }
+    }
+    // fill the tables (stream-ordered after any launch still reading them)
+    b->cur_at_fill.resize(b->members.size());
+    for (size_t k = 0; k < b->members.size(); k++) b->cur_at_fill[k] = b->members[k]->cur;
+    for (auto &g : b->groups) {
+        std::vector<BatchInst> inst(g.n_inst);
+        std::vector<int32_t> begin(g.n_inst + 1, 0);
+        for (int k = 0; k < g.n_inst; k++) {
+            sdugks_t *h = b->members[g.members[k]];
+            BatchInst &e = inst[k];
+            e.m = h->dm;
+            e.t = h->dt;
+            for (int p = 0; p < 2; p++) {
+                e.f[p] = h->base + h->L.off_f[p];
+                e.W[p] = h->at<double>(h->L.off_W[p]);
+                e.G[p] = h->at<double>(h->L.off_G[p]);
+            }
+            e.parity0 = h->cur;
+            e.lagged = h->macro == SDUGKS_MACRO_LAGGED;
+            begin[k + 1] = begin[k] + h->mb.n_tiles;
+        }
+        const int32_t count[2] = {g.n_inst, g.n_tiles};
+        HIPCHK(hipMemcpyAsync(g.d_inst, inst.data(), inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(g.d_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(g.d_count, count, sizeof count, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+    }
+    return SDUGKS_OK;
+}
+
+int batch_launch(sdugks_batch_t *b, int parity)
+{
+    for (auto &g : b->groups) {
+        BatchTable tab{g.d_inst, g.d_begin, g.d_count};
+        HIPCHK(launch_step_batch(tab, g.D, g.dev32, parity, g.cap_tiles, g.lds, g.block, b->stream));
+    }
+    return SDUGKS_OK;
+}
+
+// Order the batch stream after the members' streams (before) or the members'
+// streams after the batch stream (after).
+int batch_join(sdugks_batch_t *b, bool before)
+{
+    for (sdugks_t *h : b->members) {
+        if (h->stream == b->stream) continue;
+        if (before) {
+            HIPCHK(hipEventRecord(b->ev, h->stream));
+            HIPCHK(hipStreamWaitEvent(b->stream, b->ev, 0));
+        } else {
+            HIPCHK(hipEventRecord(b->ev, b->stream));
+            HIPCHK(hipStreamWaitEvent(h->stream, b->ev, 0));
+        }
+    }
+    return SDUGKS_OK;
+}
+
+int batch_check_members(sdugks_t *const *members, int32_t n)
+{
+    if (!members || n <= 0) return fail(SDUGKS_EINVAL, "bad batch members");
+    for (int32_t k = 0; k < n; k++) {
+        if (!members[k]) return fail(SDUGKS_EINVAL, "null batch member");
+        if (members[k]->mb.n_tiles == 0) return fail(SDUGKS_EINVAL, "batch members need the fused step");
+        if (members[k]->diverged) return fail(SDUGKS_EDIVERGED, "a batch member is not finite");
+        for (int32_t j = 0; j < k; j++)
+            if (members[j] == members[k]) return fail(SDUGKS_EINVAL, "a handle appears twice in a batch");
+        if (members[k]->device != members[0]->device) return fail(SDUGKS_EINVAL, "batch members on different devices");
+    }
+    return SDUGKS_OK;
+}
+
+}  // namespace
+
 int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugks_batch_t **out)
 {
-    if (!members || n <= 0 || !out) return fail(SDUGKS_EINVAL, "bad batch arguments");
+    if (!out) return fail(SDUGKS_EINVAL, "null out");
+    *out = nullptr;
+    int rc = batch_check_members(members, n);
+    if (rc) return rc;
     sdugks_batch_t *b = new (std::nothrow) sdugks_batch_t();
     if (!b) return fail(SDUGKS_ENOMEM, "host allocation failed");
+    b->device = members[0]->device;
+    HIPCHK(hipSetDevice(b->device));
     b->members.assign(members, members + n);
-    b->stream = (hipStream_t)stream;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess) { delete b; return fail(SDUGKS_EHIP, "stream creation failed"); }
+        b->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&b->ev, hipEventDisableTiming) != hipSuccess) {
+        sdugks_batch_destroy(b);
+        return fail(SDUGKS_EHIP, "event creation failed");
+    }
+    rc = batch_build(b);
+    if (rc) { sdugks_batch_destroy(b); return rc; }
     *out = b;
     return SDUGKS_OK;
+}
+
+int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_t n)
+{
+    if (!b) return fail(SDUGKS_EINVAL, "null batch");
+    int rc = batch_check_members(members, n);
+    if (rc) return rc;
+    HIPCHK(hipSetDevice(b->device));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->members.assign(members, members + n);
+    return batch_build(b);
 }
 
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
 {
     if (!b) return fail(SDUGKS_EINVAL, "null batch");
-    for (int64_t k = 0; k < n; k++)
-        for (sdugks_t *h : b->members) {
-            int rc = sdugks_step(h, 1);
+    if (n < 0) return fail(SDUGKS_EINVAL, "negative step count");
+    for (sdugks_t *h : b->members)
+        if (h->diverged) return fail(SDUGKS_EDIVERGED, "a batch member is not finite");
+    if (n == 0) return SDUGKS_OK;
+    HIPCHK(hipSetDevice(b->device));
+    // a member stepped alone since the table was filled: refresh its buffer index
+    for (size_t k = 0; k < b->members.size(); k++)
+        if (b->members[k]->cur != b->cur_at_fill[k]) {
+            int rc = batch_build(b);
             if (rc) return rc;
+            break;
         }
+    int rc = batch_join(b, true);
+    if (rc) return rc;
+    int64_t pairs = n / 2;
+    if (pairs > 0) {
+        if (!b->exec) {
+            HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            int r0 = batch_launch(b, 0), r1 = r0 ? r0 : batch_launch(b, 1);
+            hipGraph_t gr = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &gr);
+            if (r1) { if (gr) hipGraphDestroy(gr); return r1; }
+            if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+            b->graph = gr;
+            HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        }
+        for (int64_t k = 0; k < pairs; k++) HIPCHK(hipGraphLaunch(b->exec, b->stream));
+    }
+    if (n & 1) {
+        rc = batch_launch(b, 0);
+        if (rc) return rc;
+    }
+    rc = batch_join(b, false);
+    if (rc) return rc;
+    for (sdugks_t *h : b->members) {
+        h->cur ^= (int)(n & 1);
+        h->step += n;
+    }
+    if (n & 1) return batch_build(b);          // every member's buffer index flipped
     return SDUGKS_OK;
 }
 
 int sdugks_batch_destroy(sdugks_batch_t *b)
 {
+    if (!b) return SDUGKS_OK;
+    hipSetDevice(b->device);
+    if (b->stream) hipStreamSynchronize(b->stream);
+    batch_release_graph(b);
+    batch_release_groups(b);
+    if (b->ev) hipEventDestroy(b->ev);
+    if (b->own_stream) hipStreamDestroy(b->stream);
     delete b;
     return SDUGKS_OK;
 }

@@ -52,6 +52,25 @@ struct DevTiles {
     const float *lw32;                  // deviation form
 };
 
+// One member of a batched launch: its mesh, tiles, both ping-pong buffers
+// and the buffer index it reads at parity 0.
+struct BatchInst {
+    DevMesh m;
+    DevTiles t;
+    void *f[2];
+    double *W[2];
+    double *G[2];
+    int32_t parity0, lagged;
+};
+
+// Device-side batch table: count = {members, total tiles}; tile_begin has
+// members + 1 entries.
+struct BatchTable {
+    const BatchInst *inst;
+    const int32_t *tile_begin;
+    const int32_t *count;
+};
+
 struct DevScratch {
     double *fbp;                        // [9][np] fbar+ at the cell centres
     double *sg;                         // [18][np] its least-squares gradient (x rows 0..8, y rows 9..17)
@@ -64,6 +83,9 @@ hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScra
 hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
                              int block, hipStream_t st);
 size_t step_tiled_lds_bytes(const DevTiles &t, int dev32);
+// Batched fused step over the tiles of all members (same D class and storage).
+hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity, int cap_tiles, size_t lds,
+                             int block, hipStream_t st);
 // Deterministic reductions of the residual / mass / finiteness check: writes
 // out4 = {sum |u-u_snap|^2, sum |u_snap|^2, sum V rho, count of non-finite}.
 // snap = [2][np] (U, V); update_snap re-snapshots.

@@ -75,16 +75,12 @@ __device__ __forceinline__ double ex_rt(int i) { return (double)((0x20919 >> (2 
 __device__ __forceinline__ double ey_rt(int i) { return (double)((0x02865 >> (2 * i) & 3) - 1); }
 __device__ __forceinline__ double w_rt(int i) { return i == 0 ? 4.0 / 9 : (i < 5 ? 1.0 / 9 : 1.0 / 36); }
 
+// One time step of tile t of one instance (the whole workgroup takes part).
 template <int D, bool DEV>
-__global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevState s, int lagged)
+__device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, const DevState &s, int lagged, int t)
 {
     using R = typename std::conditional<DEV, float, double>::type;   // storage / face arithmetic
     extern __shared__ double smem[];
-    // Workgroups are dealt round-robin to the XCDs; give XCD x the contiguous
-    // tile range [x * per, (x + 1) * per).
-    const int per = (tl.n_tiles + kXcds - 1) / kXcds;
-    const int t = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-    if (t >= tl.n_tiles) return;
     const int *hd = tl.hdr + 8 * t;
     const int g0 = hd[0], nt = hd[1], na = nt + hd[2], nl = na + hd[3];
     const int P = tl.nl_max, P1 = tl.na_max;
@@ -306,6 +302,50 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
     }
 }
 
+// Workgroups are dealt round-robin to the XCDs: block b runs on XCD b % 8.
+// Give XCD x the contiguous range [x * per, (x + 1) * per) of a tile sequence.
+__device__ __forceinline__ int xcd_tile(int n)
+{
+    const int per = (n + kXcds - 1) / kXcds;
+    return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
+template <int D, bool DEV>
+__global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevState s, int lagged)
+{
+    const int t = xcd_tile(tl.n_tiles);
+    if (t >= tl.n_tiles) return;
+    step_tile<D, DEV>(m, tl, s, lagged, t);
+}
+
+// Batched step: the tiles of all instances form one sequence (instance k owns
+// [tile_begin[k], tile_begin[k + 1])); the grid covers a fixed capacity and
+// the live count is read from the device table, so the table can change
+// between launches of a captured graph.  parity selects each instance's
+// ping-pong buffers: it reads buffer (parity0 ^ parity).
+template <int D, bool DEV>
+__global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
+{
+    const int total = tab.count[1];
+    const int cap = (int)gridDim.x;
+    const int gt = xcd_tile(cap);
+    if (gt >= total) return;
+    int lo = 0, hi = tab.count[0] - 1;          // last k with tile_begin[k] <= gt
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab.tile_begin[mid] <= gt) lo = mid; else hi = mid - 1;
+    }
+    const BatchInst &in = tab.inst[lo];
+    const int p = in.parity0 ^ parity;
+    DevState s;
+    s.W = in.W[p]; s.G = in.G[p]; s.Wo = in.W[p ^ 1]; s.Go = in.G[p ^ 1];
+    s.f = reinterpret_cast<const double *>(in.f[p]);
+    s.fo = reinterpret_cast<double *>(in.f[p ^ 1]);
+    s.f32 = reinterpret_cast<const float *>(in.f[p]);
+    s.fo32 = reinterpret_cast<float *>(in.f[p ^ 1]);
+    step_tile<D, DEV>(in.m, in.t, s, in.lagged, gt - tab.tile_begin[lo]);
+}
+
 }  // namespace
 
 size_t step_tiled_lds_bytes(const DevTiles &t, int dev32)
@@ -327,6 +367,20 @@ hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState
     } else {
         if (dev32) hipLaunchKernelGGL((k_step_tiled<4, true>), grid, blk, lds, st, m, t, s, lagged);
         else hipLaunchKernelGGL((k_step_tiled<4, false>), grid, blk, lds, st, m, t, s, lagged);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity, int cap_tiles, size_t lds,
+                             int block, hipStream_t st)
+{
+    const dim3 grid((unsigned)((cap_tiles + kXcds - 1) / kXcds * kXcds)), blk(block);
+    if (D <= 3) {
+        if (dev32) hipLaunchKernelGGL((k_step_batch<3, true>), grid, blk, lds, st, tab, parity);
+        else hipLaunchKernelGGL((k_step_batch<3, false>), grid, blk, lds, st, tab, parity);
+    } else {
+        if (dev32) hipLaunchKernelGGL((k_step_batch<4, true>), grid, blk, lds, st, tab, parity);
+        else hipLaunchKernelGGL((k_step_batch<4, false>), grid, blk, lds, st, tab, parity);
     }
     return hipGetLastError();
 }

@@ -60,6 +60,7 @@ _sig = {
     "sdugks_destroy": [_P],
     "sdugks_last_error": [],
     "sdugks_batch_create": [_P, C.c_int32, _P, _P],
+    "sdugks_batch_set_members": [_P, _P, C.c_int32],
     "sdugks_batch_step": [_P, C.c_int64],
     "sdugks_batch_destroy": [_P],
     "sdugks_debug_poison": [_P, C.c_int32, C.c_int32],
@@ -227,16 +228,23 @@ class Solver:
 
 
 class Batch:
-    """Many instances advanced together (the members stay usable alone)."""
+    """Many instances advanced together by one launch per step (the members
+    stay usable alone).  With no stream given the library makes its own."""
 
     def __init__(self, members, stream=None):
-        import torch
         self.members = list(members)
         arr = (C.c_void_p * len(self.members))(*[m.handle for m in self.members])
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = stream
         b = C.c_void_p()
-        _check(_lib.sdugks_batch_create(arr, len(self.members), C.c_void_p(self.stream.cuda_stream), C.byref(b)))
+        _check(_lib.sdugks_batch_create(arr, len(self.members),
+                                        C.c_void_p(stream.cuda_stream) if stream is not None else None, C.byref(b)))
         self._b = b
+
+    def set_members(self, members):
+        members = list(members)
+        arr = (C.c_void_p * len(members))(*[m.handle for m in members])
+        _check(_lib.sdugks_batch_set_members(self._b, arr, len(members)))
+        self.members = members
 
     def step(self, n=1):
         _check(_lib.sdugks_batch_step(self._b, int(n)))

@@ -1,0 +1,127 @@
+"""Batched form on the GPU: many uneven instances advanced by one launch per
+step (replayed from a captured graph) give bit-identical states to the same
+instances stepped alone, whatever the membership changes in between."""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_07347_amd import sdugks
+    return sdugks
+
+
+def members(sd):
+    """Uneven instances: quads and triangles, FP64 and FP32 deviation storage,
+    different viscosities, lids and tile schedules."""
+    specs = [
+        (meshgen.cavity(23), dict(nu=1e-3)),
+        (meshgen.cavity(40, U=0.05), dict(nu=4e-4, tile_cells=16, block_threads=64)),
+        (meshgen.cavity(64), dict(nu=2e-4, precision=sd.FP32DEV)),
+        (meshgen.cylinder_ogrid(48, 16, seed=3), dict(nu=2.5e-3, u0=0.1)),
+        (meshgen.jittered_periodic_triangles(12, seed=4), dict(nu=4e-3, precision=sd.FP32DEV)),
+        (meshgen.couette(4, 32), dict(nu=1e-2, macro=sd.MACRO_LAGGED, cfl=0.3)),
+    ]
+    return specs
+
+
+def make(sd, specs, seed):
+    out = []
+    for k, ((mesh, bcs), kw) in enumerate(specs):
+        s = sd.Solver(mesh, bcs, cfl=kw.pop("cfl", 0.5), **kw)
+        f, W, _ = meshgen.random_state(s.n_cells, seed=seed + k, amp=0.01)
+        s.set_state(f, W)
+        out.append(s)
+    return out
+
+
+def states(solvers):
+    return [s.state() for s in solvers]
+
+
+def assert_same(a, b):
+    for sa, sb in zip(a, b):
+        for x, y in zip(sa, sb):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 40])
+def test_batch_equals_alone(sd, n):
+    alone = make(sd, members(sd), seed=100)
+    batched = make(sd, members(sd), seed=100)
+    for s in alone:
+        s.step(n)
+    b = sd.Batch(batched)
+    b.step(n)
+    assert_same(states(alone), states(batched))
+    b.close()
+
+
+def test_graph_replays_with_eager_work_between(sd):
+    """Graph replays interleaved with members stepped alone, residual and mass
+    reductions and host synchronisations: every replay matches the eager run."""
+    alone = make(sd, members(sd), seed=200)
+    batched = make(sd, members(sd), seed=200)
+    b = sd.Batch(batched)
+    for rnd in range(5):
+        for s in alone:
+            s.step(6)
+        b.step(6)
+        assert_same(states(alone), states(batched))
+        # eager work on one member between replays
+        alone[1].step(3)
+        batched[1].step(3)
+        alone[1].residual()
+        batched[1].residual()
+        assert batched[2].mass() == alone[2].mass()
+    b.close()
+
+
+def test_continuous_batching_membership_changes(sd):
+    """Members join and leave between steps (admission / retirement): results
+    stay bitwise those of stepping each instance alone."""
+    specs = members(sd)
+    alone = make(sd, specs, seed=300)
+    batched = make(sd, members(sd), seed=300)
+    b = sd.Batch(batched[:2])
+    plan = [[0, 1], [0, 1, 2, 3], [1, 3, 4], [0, 1, 2, 3, 4, 5], [5], [2, 4]]
+    for ids in plan:
+        b.set_members([batched[k] for k in ids])
+        b.step(5)
+        for k in ids:
+            alone[k].step(5)
+    assert_same(states(alone), states(batched))
+    b.close()
+
+
+def test_batch_rejects_two_kernel_members(sd):
+    hexes = sd.Solver(*meshgen.hexagon_strip(4, 3), nu=0.01)
+    cav = sd.Solver(*meshgen.cavity(8), nu=0.01)
+    with pytest.raises(sd.SdugksError):
+        sd.Batch([cav, hexes])
+    with pytest.raises(sd.SdugksError):
+        sd.Batch([cav, cav])
+
+
+def test_batch_refuses_diverged_member(sd):
+    a = sd.Solver(*meshgen.cavity(12), nu=2e-3)
+    c = sd.Solver(*meshgen.cavity(10), nu=2e-3)
+    b = sd.Batch([a, c])
+    b.step(4)
+    a.poison(5, 2)
+    a.step(1)
+    with pytest.raises(sd.SdugksError):
+        a.residual()
+    with pytest.raises(sd.SdugksError) as ei:
+        b.step(2)
+    assert ei.value.code == sd.EDIVERGED
+    b.set_members([c])
+    b.step(2)
+    c.residual()
+    b.close()
