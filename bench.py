@@ -1,18 +1,26 @@
 """Benchmark of the sDUGKS step on one MI355X.
 
-Workload: lid-driven cavity, 256 x 256 tanh-stretched quads (stretching 1.5),
-Re = 1000 (lid 0.1, nu = 1e-4), CFL 0.5, D2Q9, FP64, from rest.  A step is
-one full time step of the scheme (every kernel of the hot path) with the
-convergence residual evaluated every 1000 steps, as in the paper's cavity
-case.  Prints one JSON line: MLUPS (cell updates per second / 1e6), the HBM
-roofline of the step kernels, and the CPU oracle timed on a bounded sample.
+Headline workload: lid-driven cavity, 256 x 256 tanh-stretched quads
+(stretching 1.5), Re = 1000 (lid 0.1, nu = 1e-4), CFL 0.5, D2Q9, FP64, from
+rest.  A step is one full time step of the scheme (the fused step kernel) with
+the convergence residual evaluated every 1000 steps, as in the paper's cavity
+case.  The tile schedule comes from the autotuner.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+The one JSON line also carries: the same workload with FP32-deviation storage;
+the batched form on 64 uneven cavities (edge log-uniform in [32, 512] cells,
+Re uniform in [100, 5000], FP32 deviation storage) against stepping the same
+instances one after another; the HBM roofline of the step kernel; and the
+CPU oracle timed on a bounded sample of the headline workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+    python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -22,58 +30,79 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 RESIDUAL_INTERVAL = 1000
-# Compulsory bytes per cell update of the fused FP64 step on quads, same-step
-# macroscopic flux: f (72 B) and W (24 B) read and written once, plus the
-# geometry read once (centroid 16, 1/V 8, four neighbours x (index 4 + two
-# LSQ weights 16), two faces x (owner/neighbour 8 + l*n 16 + midpoint 16)).
-ALG_BYTES_PER_CELL = 2 * (72 + 24) + 184
+# Compulsory bytes per cell update of the step on quads with the same-step
+# macroscopic flux: f and W read and written once (FP64: 2 * (72 + 24);
+# FP32 deviation: 2 * (36 + 24)) plus the geometry read once (centroid 16,
+# 1/V 8, four neighbours x (index 4 + two LSQ weights 16), two faces x
+# (owner/neighbour 8 + l*n 16 + midpoint 16) = 184).
+ALG_BYTES = {"f64": 2 * (72 + 24) + 184, "fp32dev": 2 * (36 + 24) + 184}
+KERNEL_SRC = os.path.join(ROOT, "paper_2007_07347_amd", "csrc", "step_tiled.hip")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=4000)
-    p.add_argument("--warmup", type=int, default=200)
+    p.add_argument("--steps", type=int, default=6000)
+    p.add_argument("--warmup", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-extra", action="store_true", help="headline workload only")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     return p.parse_args()
 
 
-def cpu_baseline(mesh, bcs, kw, target_s):
-    import oracle
-    o = oracle.Oracle(mesh, bcs, **kw)
-    t = time.perf_counter()
-    o.step(5)
-    per_step = (time.perf_counter() - t) / 5
-    n = max(5, int(target_s / per_step))
-    t = time.perf_counter()
-    o.step(n)
-    el = time.perf_counter() - t
-    return {"value": o.n_cells * n / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"cavity 256x256 FP64, {n} steps from step 5 of a run from rest (single thread, gcc -O2)"}
+def kernel_hash():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()[:16]
 
 
-def main():
-    a = parse()
-    if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described, not built.",
-              file=sys.stderr)
-        sys.exit(2)
+def measured_traffic(workload):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("kernel_sha1") != kernel_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def copy_calibration(mb):
     import torch
-    import meshgen
-    from paper_2007_07347_amd import sdugks
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
 
-    torch.cuda.set_device(0)
+
+def time_steps(step, n, stream=None):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    step(n)
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
+def headline(sdugks, autotune, meshgen, a, precision):
+    import torch
     mesh, bcs = meshgen.cavity(256, beta=1.5, U=0.1)
-    kw = dict(nu=0.1 / 1000, cfl=0.5)
-    s = sdugks.Solver(mesh, bcs, **kw)
+    kw = dict(nu=0.1 / 1000, cfl=0.5, precision=precision)
+    sched, _ = autotune.autotune(mesh, bcs, steps=200, **kw)
+    s = sdugks.Solver(mesh, bcs, **sched, **kw)
     nc = s.n_cells
     s.step(a.warmup)
     torch.cuda.synchronize()
-
+    done, eps = 0, None
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    done = 0
-    eps = None
     t0 = time.perf_counter()
     start.record()
     while done < a.steps:
@@ -86,17 +115,99 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(end)
-    mlups = nc * a.steps / (ms / 1e3) / 1e6
-
-    # per-kernel durations with HIP events on the solver's stream
+    # per-launch HIP events on the solver's stream, same workload, after the timed region
     kt = s.step_profiled(min(a.steps, 2000))
-    step_ms = sum(kt.values())
-    dominant = max(kt, key=kt.get)
-    achieved = ALG_BYTES_PER_CELL * nc / (step_ms / 1e3) / 1e9
-    roof = {"bound": "hbm", "kernel": "+".join(kt), "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_cell": ALG_BYTES_PER_CELL, "kernel_ms": {k: round(v, 5) for k, v in kt.items()},
-            "dominant": dominant}
+    return s, mesh, bcs, kw, sched, nc, ms, wall, eps, kt
+
+
+def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
+    """64 uneven cavities, batched (one launch per step, graph replay) against
+    stepping each instance after the other."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    sizes = meshgen.log_uniform_int(rng, 32, 512, size=n_inst)
+    res = rng.uniform(100.0, 5000.0, size=n_inst)
+    solvers, cells = [], 0
+    for n, re in zip(sizes, res):
+        mesh, bcs = meshgen.cavity(int(n), beta=1.5, U=0.1)
+        solvers.append(sdugks.Solver(mesh, bcs, nu=0.1 / re, cfl=0.5, precision=sdugks.FP32DEV,
+                                     tile_cells=32, block_threads=128))
+        cells += int(n) * int(n)
+    b = sdugks.Batch(solvers)
+    b.step(20)
+    for s in solvers:
+        s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    ms_b = (time.perf_counter() - t0) * 1e3
+
+    def loop(n):
+        for _ in range(n):
+            for s in solvers:
+                s.step(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loop(steps)
+    torch.cuda.synchronize()
+    ms_l = (time.perf_counter() - t0) * 1e3
+    b.close()
+    out = {"workload": "64 tanh cavities, edge log-uniform in [32, 512], Re uniform in [100, 5000], FP32 deviation",
+           "seed": seed, "cells": cells, "steps": steps,
+           "batched_mlups": round(cells * steps / (ms_b / 1e3) / 1e6, 1), "batched_ms_per_step": round(ms_b / steps, 4),
+           "per_instance_loop_mlups": round(cells * steps / (ms_l / 1e3) / 1e6, 1),
+           "per_instance_loop_ms_per_step": round(ms_l / steps, 4)}
+    for s in solvers:
+        s.close()
+    return out
+
+
+def cpu_baseline(mesh, bcs, kw, target_s):
+    import oracle
+    kw = {k: v for k, v in kw.items() if k in ("nu", "cfl")}
+    o = oracle.Oracle(mesh, bcs, **kw)
+    t = time.perf_counter()
+    o.step(5)
+    per_step = (time.perf_counter() - t) / 5
+    n = max(5, int(target_s / per_step))
+    t = time.perf_counter()
+    o.step(n)
+    el = time.perf_counter() - t
+    return {"value": round(o.n_cells * n / el / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"cavity 256x256 Re 1000 FP64, {n} steps (from step 5 of a run from rest), single thread, gcc -O2"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described, not built.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if a.copy_calibration:
+        copy_calibration(a.copy_calibration)
+        return
+    import meshgen
+    from paper_2007_07347_amd import autotune, sdugks
+
+    s, mesh, bcs, kw, sched, nc, ms, wall, eps, kt = headline(sdugks, autotune, meshgen, a, sdugks.FP64)
+    mlups = nc * a.steps / (ms / 1e3) / 1e6
+    kname = max(kt, key=kt.get)
+    # one launch of the step kernel per step: its average duration is the timed
+    # region (HIP events on the solver's stream) over the step count (the six
+    # residual reductions add about 0.01 us per step)
+    k_ms = ms / a.steps
+    achieved = ALG_BYTES["f64"] * nc / (k_ms / 1e3) / 1e9
+    traffic = measured_traffic("cavity256_f64")
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_cell": ALG_BYTES["f64"], "cells_per_launch": nc, "kernel_ms": round(k_ms, 5),
+            "kernel_ms_event_per_launch": round(kt[kname], 5),
+            "working_set_MB": round(sdugks.state_bytes(mesh, bcs, **kw, **sched) / 1e6, 1),
+            "note": "working set fits the 256 MB Infinity Cache"}
     out = {
         "metric": "MLUPS (D2Q9 cell-updates/s) & %HBM peak; p50/p99 time-to-steady under load",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -104,10 +215,21 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "lid-driven cavity 256x256 tanh(1.5) quads, Re 1000, CFL 0.5, D2Q9, FP64, "
                                "residual every 1000 steps",
-                   "cells": nc, "dt": s.dt, "tau": s.tau, "residual_at_end": eps},
+                   "cells": nc, "dt": s.dt, "tau": s.tau, "schedule": sched, "residual_at_end": eps},
         "roofline": roof,
         "wall_s": round(wall, 3),
     }
+    s.close()
+    if not a.no_extra:
+        s32, _, _, _, sched32, _, ms32, _, _, kt32 = headline(sdugks, autotune, meshgen, a, sdugks.FP32DEV)
+        k32 = ms32 / a.steps
+        out["fp32dev"] = {"value": round(nc * a.steps / (ms32 / 1e3) / 1e6, 1), "unit": "MLUPS",
+                          "ms_per_step": round(ms32 / a.steps, 5), "schedule": sched32, "kernel_ms": round(k32, 5),
+                          "achieved_GBs": round(ALG_BYTES["fp32dev"] * nc / (k32 / 1e3) / 1e9, 1),
+                          "alg_bytes_per_cell": ALG_BYTES["fp32dev"],
+                          "traffic": measured_traffic("cavity256_fp32dev")}
+        s32.close()
+        out["batch"] = batch_form(sdugks, autotune, meshgen)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, bcs, kw, a.cpu_seconds)
     print(json.dumps(out), flush=True)
