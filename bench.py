@@ -9,8 +9,10 @@ case.  The tile schedule comes from the autotuner.
 The one JSON line also carries: the same workload with FP32-deviation storage;
 the batched form on 64 uneven cavities (edge log-uniform in [32, 512] cells,
 Re uniform in [100, 5000], FP32 deviation storage) against stepping the same
-instances one after another; the HBM roofline of the step kernel; and the
-CPU oracle timed on a bounded sample of the headline workload.
+instances one after another; the continuous-batching serving loop on a finite
+seeded request trace with p50/p99 time-to-steady, against the per-case FP64
+loop; the HBM roofline of the step kernel; and the CPU oracle timed on a
+bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
     python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
@@ -164,6 +166,27 @@ def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
     return out
 
 
+def serving(meshgen, seed=7, n_requests=24, step_cap=150_000):
+    """Continuous-batching serving loop on a finite seeded trace (Poisson
+    arrivals at 20 per second, Couette / cavity / cylinder requests) against
+    the plain per-case FP64 loop on the same trace."""
+    from paper_2007_07347_amd import sdugks, serve
+    trace = meshgen.serving_trace(seed=seed, n_requests=n_requests)
+    rq = [serve.Request(r["rid"], r["arrival"], r["mesh"], r["bcs"], r["params"], r["kind"], r["n_cells"])
+          for r in trace]
+    budget = 8 << 30
+    res_b, st_b = serve.Server(serve.GpuBackend(), budget_bytes=budget, interval=1000, tol=1e-7,
+                               step_cap=step_cap).run(rq)
+    res_s, st_s = serve.SequentialServer(serve.GpuBackend(precision=sdugks.FP64), budget_bytes=budget, interval=1000,
+                                         tol=1e-7, step_cap=step_cap).run(rq)
+    r3 = lambda x: None if x is None else round(x, 3)  # noqa: E731
+    return {"workload": f"{n_requests} requests (Couette 4xN N in [8,32], cavity N^2 N in [16,64], cylinder O-grid "
+                        f"1k-20k cells; Re 10-400, cylinders 10-40), Poisson 20/s, seed {seed}, residual 1e-7, "
+                        f"cap {step_cap} steps, HBM budget 8 GiB",
+            "batched_fp32dev": {k: (r3(v) if isinstance(v, float) else v) for k, v in st_b.items()},
+            "per_case_fp64_loop": {k: (r3(v) if isinstance(v, float) else v) for k, v in st_s.items()}}
+
+
 def cpu_baseline(mesh, bcs, kw, target_s):
     import oracle
     kw = {k: v for k, v in kw.items() if k in ("nu", "cfl")}
@@ -230,6 +253,7 @@ def main():
                           "traffic": measured_traffic("cavity256_fp32dev")}
         s32.close()
         out["batch"] = batch_form(sdugks, autotune, meshgen)
+        out["serving"] = serving(meshgen)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, bcs, kw, a.cpu_seconds)
     print(json.dumps(out), flush=True)

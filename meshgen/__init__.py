@@ -293,3 +293,40 @@ def inlet_outlet_box(nx, ny, u_in=0.05):
     ys = tanh_nodes(ny, 1.0)
     mesh = structured(xs, ys, tag_bottom=0, tag_right=1, tag_top=0, tag_left=2)
     return mesh, [bc(WALL), bc(OUTLET), bc(INLET, rho=1.0, u=u_in, v=0.0)]
+
+
+def serving_trace(seed=7, n_requests=24, rate=20.0, couette_n=(8, 32), cavity_n=(16, 64),
+                  cylinder_cells=(1_000, 20_000), re_range=(10.0, 400.0), cylinder_re=(10.0, 40.0)):
+    """Seeded finite trace of steady-state solve requests: Poisson arrivals at
+    `rate` per second, kinds uniform over Couette (4 x N, N log-uniform),
+    lid-driven cavity (N x N tanh mesh, N log-uniform) and cylinder O-grid
+    (cells log-uniform, n_theta : n_r = 8 : 5, triangles), Reynolds numbers
+    uniform (cylinders kept in the steady range).  Returns a list of dicts
+    {rid, arrival, kind, mesh, bcs, params, n_cells}; params hold nu (lid or
+    free-stream speed 0.1 over the length scale 1), cfl 0.5 and u0."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for rid in range(n_requests):
+        t += rng.exponential(1.0 / rate)
+        kind = ("couette", "cavity", "cylinder")[int(rng.integers(0, 3))]
+        if kind == "couette":
+            n = int(log_uniform_int(rng, *couette_n))
+            re = float(rng.uniform(re_range[0], min(re_range[1], 40.0)))
+            mesh, bcs = couette(4, n, U=0.1)
+            params = {"nu": 0.1 / re, "cfl": 0.5}
+        elif kind == "cavity":
+            n = int(log_uniform_int(rng, *cavity_n))
+            re = float(rng.uniform(*re_range))
+            mesh, bcs = cavity(n, beta=1.5, U=0.1)
+            params = {"nu": 0.1 / re, "cfl": 0.5}
+        else:
+            cells = float(np.exp(rng.uniform(math.log(cylinder_cells[0]), math.log(cylinder_cells[1]))))
+            n_r = max(4, int(round(math.sqrt(cells * 5.0 / 16.0))))
+            n_theta = max(8, int(round(n_r * 8.0 / 5.0)))
+            re = float(rng.uniform(*cylinder_re))
+            mesh, bcs = cylinder_ogrid(n_theta, n_r, seed=int(rng.integers(0, 2**31)), U=0.1)
+            params = {"nu": 0.1 * 1.0 / re, "cfl": 0.5, "u0": 0.1}
+        out.append({"rid": rid, "arrival": t, "kind": kind, "mesh": mesh, "bcs": bcs, "params": params,
+                    "n_cells": len(mesh["cell_ptr"]) - 1, "re": re})
+    return out

@@ -1,0 +1,259 @@
+"""Serving loop: continuous batching of steady-state sDUGKS solves.
+
+Requests (a mesh, its boundary table, the flow parameters) arrive over time.
+The scheduler keeps a FIFO queue, admits the head of the queue as soon as a
+slot is free and the request's device bytes fit the remaining HBM budget,
+advances every admitted instance together (one batched launch per step,
+replayed from a captured graph) in chunks of `interval` steps, then polls
+each instance's velocity residual (the convergence test of the paper's
+cavity case, checked every 1000 steps there) and retires instances that
+converged, diverged (non-finite state) or hit their step cap.  Retirement
+frees the slot and the memory, and the next queued request is admitted
+before the next chunk: requests that arrive while others run join the
+running batch.
+
+Time-to-steady of a request = completion time - arrival time (queueing
+included).  The backend interface keeps the policy testable without a GPU:
+
+    backend.bytes(req) -> int                 device bytes the instance needs
+    backend.create(req) -> instance           instance.step(n), .residual(),
+                                              .macros(), .close(), .n_cells
+    backend.batch(instances) -> batch         batch.step(n), .set_members(list),
+                                              .close()
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from typing import Any, Callable, List, Optional
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                  # seconds after the start of the trace
+    mesh: Any
+    bcs: Any
+    params: dict
+    kind: str = ""
+    n_cells: int = 0
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    kind: str
+    n_cells: int
+    status: str                     # "converged", "not_converged", "diverged", "rejected"
+    arrival: float
+    admitted: float
+    finished: float
+    steps: int
+    residual: float
+    macros: Optional[tuple] = None
+
+    @property
+    def time_to_steady(self):
+        return self.finished - self.arrival
+
+
+class Server:
+    """Continuous-batching scheduler over a backend (see module docstring).
+
+    budget_bytes: device memory the admitted instances may hold together.
+    max_slots:    admitted instances at most.
+    interval:     steps between residual checks (the paper checks every 1000).
+    tol:          residual that counts as steady.
+    step_cap:     steps after which an instance is retired as not converged.
+    keep_macros:  copy (rho, u, v) out of each retired instance.
+    """
+
+    def __init__(self, backend, budget_bytes, max_slots=64, interval=1000, tol=1e-7, step_cap=200_000,
+                 keep_macros=False, clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.interval = int(interval)
+        self.tol = float(tol)
+        self.step_cap = int(step_cap)
+        self.keep_macros = keep_macros
+        self.clock = clock
+        self.sleep = sleep
+        self.log: List[tuple] = []          # (time, event, rid, extra)
+
+    def run(self, requests: List[Request]):
+        """Serve a finite trace; returns (results in request order, stats)."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        queue: List[Request] = []
+        active = []                         # [req, instance, bytes, admitted_at, steps]
+        results = {}
+        used = 0
+        batch = None
+        members_changed = False
+        cell_updates = 0
+        t0 = self.clock()
+        now = lambda: self.clock() - t0     # noqa: E731
+        while pending or queue or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                queue.append(pending.pop(0))
+            # admission, FIFO: the head waits until it fits (no overtaking)
+            while queue and len(active) < self.max_slots:
+                req = queue[0]
+                need = self.backend.bytes(req)
+                if need > self.budget:
+                    queue.pop(0)
+                    results[req.rid] = Result(req.rid, req.kind, req.n_cells, "rejected", req.arrival, now(),
+                                              now(), 0, math.inf)
+                    self.log.append((now(), "reject", req.rid, need))
+                    continue
+                if used + need > self.budget:
+                    break
+                queue.pop(0)
+                inst = self.backend.create(req)
+                used += need
+                active.append([req, inst, need, now(), 0])
+                members_changed = True
+                self.log.append((now(), "admit", req.rid, need))
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
+                continue
+            if batch is None:
+                batch = self.backend.batch([a[1] for a in active])
+            elif members_changed:
+                batch.set_members([a[1] for a in active])
+            members_changed = False
+            batch.step(self.interval)
+            for a in active:
+                a[4] += self.interval
+                cell_updates += a[1].n_cells * self.interval
+            # poll every instance, then change the membership once, then free
+            keep, retired = [], []
+            for a in active:
+                req, inst, need, t_adm, steps = a
+                status = None
+                try:
+                    eps = inst.residual()
+                except Exception as e:          # non-finite state: only this request fails
+                    if getattr(e, "code", None) != -4:
+                        raise
+                    eps, status = math.nan, "diverged"
+                if status is None:
+                    if eps <= self.tol:
+                        status = "converged"
+                    elif steps >= self.step_cap:
+                        status = "not_converged"
+                if status is None:
+                    keep.append(a)
+                    continue
+                macros = inst.macros() if (self.keep_macros and status != "diverged") else None
+                results[req.rid] = Result(req.rid, req.kind, req.n_cells, status, req.arrival, t_adm, now(), steps,
+                                          eps, macros)
+                self.log.append((now(), status, req.rid, steps))
+                used -= need
+                retired.append(inst)
+            if retired:
+                # the batch drops the members before they are destroyed
+                if keep:
+                    batch.set_members([a[1] for a in keep])
+                else:
+                    batch.close()
+                    batch = None
+                for inst in retired:
+                    inst.close()
+            active = keep
+        elapsed = now()
+        out = [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+        return out, summarize(out, elapsed, cell_updates)
+
+
+def summarize(results, elapsed, cell_updates):
+    done = [r for r in results if r.status == "converged"]
+    tts = sorted(r.time_to_steady for r in done)
+
+    def pct(p):
+        if not tts:
+            return None
+        k = min(len(tts) - 1, max(0, int(math.ceil(p / 100.0 * len(tts))) - 1))
+        return tts[k]
+    return {"requests": len(results), "converged": len(done),
+            "not_converged": sum(r.status == "not_converged" for r in results),
+            "diverged": sum(r.status == "diverged" for r in results),
+            "rejected": sum(r.status == "rejected" for r in results),
+            "p50_time_to_steady_s": pct(50), "p99_time_to_steady_s": pct(99),
+            "makespan_s": elapsed, "cell_updates": cell_updates,
+            "aggregate_mlups": cell_updates / elapsed / 1e6 if elapsed > 0 else None}
+
+
+class SequentialServer(Server):
+    """The plain per-case loop: one request at a time, in arrival order, no
+    batching (the baseline the continuous batch is compared with)."""
+
+    def run(self, requests: List[Request]):
+        pending = sorted(requests, key=lambda r: r.arrival)
+        results = {}
+        cell_updates = 0
+        t0 = self.clock()
+        now = lambda: self.clock() - t0     # noqa: E731
+        for req in pending:
+            if req.arrival > now():
+                self.sleep(req.arrival - now())
+            need = self.backend.bytes(req)
+            if need > self.budget:
+                results[req.rid] = Result(req.rid, req.kind, req.n_cells, "rejected", req.arrival, now(), now(), 0,
+                                          math.inf)
+                continue
+            t_adm = now()
+            inst = self.backend.create(req)
+            steps, status, eps = 0, None, math.inf
+            while status is None:
+                inst.step(self.interval)
+                steps += self.interval
+                cell_updates += inst.n_cells * self.interval
+                try:
+                    eps = inst.residual()
+                except Exception as e:
+                    if getattr(e, "code", None) == -4:
+                        status, eps = "diverged", math.nan
+                        break
+                    raise
+                if eps <= self.tol:
+                    status = "converged"
+                elif steps >= self.step_cap:
+                    status = "not_converged"
+            macros = inst.macros() if (self.keep_macros and status != "diverged") else None
+            results[req.rid] = Result(req.rid, req.kind, req.n_cells, status, req.arrival, t_adm, now(), steps, eps,
+                                      macros)
+            inst.close()
+        elapsed = now()
+        out = [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+        return out, summarize(out, elapsed, cell_updates)
+
+
+class GpuBackend:
+    """Backend on libsdugks: one solver per request (its device memory a torch
+    tensor of sdugks_state_bytes), one batch for all admitted solvers."""
+
+    def __init__(self, precision=None, **defaults):
+        from . import sdugks
+        self.sd = sdugks
+        self.precision = sdugks.FP32DEV if precision is None else precision
+        self.defaults = defaults
+
+    def _kw(self, req):
+        kw = dict(self.defaults)
+        kw.update(req.params)
+        kw.setdefault("precision", self.precision)
+        return kw
+
+    def bytes(self, req):
+        return self.sd.state_bytes(req.mesh, req.bcs, **self._kw(req))
+
+    def create(self, req):
+        return self.sd.Solver(req.mesh, req.bcs, **self._kw(req))
+
+    def batch(self, instances):
+        return self.sd.Batch(instances)

@@ -1,0 +1,217 @@
+"""Serving scheduler on the CPU: admission by HBM budget and slots, FIFO
+order, continuous batching, failure isolation, step caps, and results that
+are the same alone and in the mix (oracle-backed instances)."""
+import math
+
+import numpy as np
+import pytest
+
+import meshgen
+from paper_2007_07347_amd.serve import Request, SequentialServer, Server, summarize
+
+
+class SimClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-4)
+
+
+class FakeInst:
+    """Converges after `need` steps; residual 1 before, 1e-9 after."""
+
+    def __init__(self, req, clock, log):
+        self.req, self.clock, self.log = req, clock, log
+        self.n_cells = req.n_cells
+        self.steps = 0
+        self.closed = False
+
+    def step(self, n):
+        assert not self.closed
+        self.steps += n
+
+    def residual(self):
+        assert not self.closed
+        if self.req.params.get("poison"):
+            e = RuntimeError("not finite")
+            e.code = -4
+            raise e
+        return 1e-9 if self.steps >= self.req.params["need"] else 1.0
+
+    def macros(self):
+        return (self.req.rid, self.steps)
+
+    def close(self):
+        self.closed = True
+
+
+class FakeBatch:
+    def __init__(self, members, clock, log):
+        self.members, self.clock, self.log = list(members), clock, log
+
+    def set_members(self, members):
+        self.members = list(members)
+
+    def step(self, n):
+        self.log.append(("batch", tuple(m.req.rid for m in self.members)))
+        cells = 0
+        for m in self.members:
+            m.step(n)
+            cells += m.n_cells
+        self.clock.t += 1e-6 * n * (1 + cells / 1000.0)   # one launch per step
+
+    def close(self):
+        self.members = []
+
+
+class FakeBackend:
+    def __init__(self, clock, cost=None):
+        self.clock, self.log, self.cost = clock, [], cost or (lambda r: r.n_cells * 100)
+        self.live = {}
+
+    def bytes(self, req):
+        return self.cost(req)
+
+    def create(self, req):
+        inst = FakeInst(req, self.clock, self.log)
+        self.live[req.rid] = inst
+        return inst
+
+    def batch(self, instances):
+        return FakeBatch(instances, self.clock, self.log)
+
+
+def reqs(specs):
+    return [Request(rid=k, arrival=a, mesh=None, bcs=None, params=p, kind="fake", n_cells=n)
+            for k, (a, n, p) in enumerate(specs)]
+
+
+def run(server_cls, specs, **kw):
+    clock = SimClock()
+    be = FakeBackend(clock, kw.pop("cost", None))
+    srv = server_cls(be, clock=clock, sleep=clock.sleep, **kw)
+    res, stats = srv.run(reqs(specs))
+    return res, stats, srv, be
+
+
+def test_budget_and_slots_respected_fifo():
+    specs = [(0.0, 100, {"need": 3000}), (0.0, 300, {"need": 1000}), (0.0, 100, {"need": 1000}),
+             (0.0, 100, {"need": 2000}), (0.001, 400, {"need": 1000})]
+    res, stats, srv, be = run(Server, specs, budget_bytes=50_000, max_slots=3, interval=1000)
+    assert stats["converged"] == 5
+    used, live, order = 0, 0, []
+    sizes = {k: n * 100 for k, (a, n, p) in enumerate(specs)}
+    for t, ev, rid, extra in srv.log:
+        if ev == "admit":
+            used += sizes[rid]
+            live += 1
+            order.append(rid)
+        elif ev == "converged":
+            used -= sizes[rid]
+            live -= 1
+        assert used <= 50_000 and live <= 3
+    assert order == sorted(order)          # FIFO: nobody overtakes the head
+
+
+def test_continuous_batching_joins_running_batch():
+    specs = [(0.0, 10, {"need": 10_000}), (0.0005, 10, {"need": 1000})]
+    res, stats, srv, be = run(Server, specs, budget_bytes=10**9, interval=1000)
+    batches = [m for kind, m in be.log if kind == "batch"]
+    assert (0, 1) in batches                 # the later request ran together with the first
+    assert res[1].finished < res[0].finished
+
+
+def test_oversized_request_rejected_others_served():
+    specs = [(0.0, 100, {"need": 1000}), (0.0, 10**6, {"need": 1000}), (0.0, 100, {"need": 2000})]
+    res, stats, srv, be = run(Server, specs, budget_bytes=10**6)
+    assert [r.status for r in res] == ["converged", "rejected", "converged"]
+
+
+def test_divergence_isolated_and_step_cap():
+    specs = [(0.0, 10, {"need": 3000}), (0.0, 10, {"need": 2000, "poison": True}), (0.0, 10, {"need": 10**9})]
+    res, stats, srv, be = run(Server, specs, budget_bytes=10**6, step_cap=5000, interval=1000)
+    assert [r.status for r in res] == ["converged", "diverged", "not_converged"]
+    assert res[0].steps == 3000 and res[2].steps == 5000
+    assert all(inst.closed for inst in be.live.values())
+
+
+def test_percentiles():
+    from paper_2007_07347_amd.serve import Result
+    rs = [Result(k, "x", 1, "converged", 0.0, 0.0, float(k + 1), 0, 0.0) for k in range(100)]
+    s = summarize(rs, 100.0, 10**8)
+    assert s["p50_time_to_steady_s"] == 50.0 and s["p99_time_to_steady_s"] == 99.0
+    assert s["aggregate_mlups"] == pytest.approx(1.0)
+
+
+def test_sequential_baseline_serves_in_arrival_order():
+    specs = [(0.0, 10, {"need": 2000}), (0.0, 10, {"need": 1000})]
+    res, stats, srv, be = run(SequentialServer, specs, budget_bytes=10**6)
+    assert res[0].finished <= res[1].admitted
+
+
+# ---- real physics on the CPU: oracle-backed instances
+class OracleInst:
+    def __init__(self, req, oracle_mod):
+        self.o = oracle_mod.Oracle(req.mesh, req.bcs, **req.params)
+        self.n_cells = self.o.n_cells
+
+    def step(self, n):
+        self.o.step(n)
+
+    def residual(self):
+        return self.o.residual()
+
+    def macros(self):
+        return self.o.macros()
+
+    def close(self):
+        pass
+
+
+class OracleBatch:
+    def __init__(self, members):
+        self.members = list(members)
+
+    def set_members(self, members):
+        self.members = list(members)
+
+    def step(self, n):
+        for m in self.members:
+            m.step(n)
+
+    def close(self):
+        self.members = []
+
+
+class OracleBackend:
+    def __init__(self, oracle_mod):
+        self.oracle = oracle_mod
+
+    def bytes(self, req):
+        return req.n_cells * 400
+
+    def create(self, req):
+        return OracleInst(req, self.oracle)
+
+    def batch(self, instances):
+        return OracleBatch(instances)
+
+
+def test_results_same_alone_and_in_the_mix(oracle_mod):
+    trace = meshgen.serving_trace(seed=3, n_requests=5, couette_n=(4, 8), cavity_n=(6, 10),
+                                  cylinder_cells=(100, 300), re_range=(5.0, 20.0), cylinder_re=(5.0, 10.0))
+    rq = [Request(r["rid"], r["arrival"], r["mesh"], r["bcs"], r["params"], r["kind"], r["n_cells"]) for r in trace]
+    clock = SimClock()
+    srv = Server(OracleBackend(oracle_mod), budget_bytes=10**9, interval=200, tol=1e-6, step_cap=4000,
+                 keep_macros=True, clock=clock, sleep=clock.sleep)
+    res, stats = srv.run(rq)
+    for r, q in zip(res, rq):
+        o = oracle_mod.Oracle(q.mesh, q.bcs, **q.params)
+        o.step(r.steps)
+        for a, b in zip(r.macros, o.macros()):
+            assert np.array_equal(a, b)
+    assert stats["converged"] + stats["not_converged"] == 5
