@@ -164,7 +164,7 @@ int build(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdug
     rc = build_mesh(mesh, bc, n_bc, prm, mb, err);
     if (rc) return fail(rc, "mesh: " + err);
     if (prm->precision == SDUGKS_FP32DEV && mb.n_tiles == 0)
-        return fail(SDUGKS_EINVAL, "SDUGKS_FP32DEV needs the fused step (polygons of at most four faces, tile_cells >= 0)");
+        return fail(SDUGKS_EINVAL, "SDUGKS_FP32DEV needs the fused step (polygons of at most four faces, at most 64 boundary-condition entries, tile_cells >= 0)");
     return SDUGKS_OK;
 }
 
@@ -323,16 +323,23 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     // geometry
     const bool dev = h->dev32(), tiled = mb.n_tiles > 0;
     {
-        std::vector<double> geo((size_t)6 * mb.D * nc);
-        const std::vector<double> *parts[6] = {&mb.lnx, &mb.lny, &mb.rsx, &mb.rsy, &mb.rox, &mb.roy};
-        for (int k = 0; k < 6; k++) std::copy(parts[k]->begin(), parts[k]->end(), geo.begin() + (size_t)k * mb.D * nc);
+        // face geometry as (x, y) pairs: rows [3][D] (l n, r_self, r_other) of np pairs each
+        const size_t D = mb.D, n_geo = 3 * D * np * 2;
+        std::vector<double> geo(n_geo, 0.0);
+        const std::vector<double> *parts[3][2] = {{&mb.lnx, &mb.lny}, {&mb.rsx, &mb.rsy}, {&mb.rox, &mb.roy}};
+        for (size_t k = 0; k < 3; k++)
+            for (size_t sl = 0; sl < D; sl++)
+                for (size_t c = 0; c < nc; c++)
+                    for (size_t e = 0; e < 2; e++)
+                        geo[((k * D + sl) * np + c) * 2 + e] = (*parts[k][e])[sl * nc + c];
+        hipError_t e;
         if (dev) {
             std::vector<float> g32(geo.begin(), geo.end());
-            rc = upload_rows(h->at<float>(L.off_geo), g32, 6 * (size_t)mb.D, nc, np, h->stream);
+            e = hipMemcpy(h->at<float>(L.off_geo), g32.data(), n_geo * sizeof(float), hipMemcpyHostToDevice);
         } else {
-            rc = upload_rows(h->at<double>(L.off_geo), geo, 6 * (size_t)mb.D, nc, np, h->stream);
+            e = hipMemcpy(h->at<double>(L.off_geo), geo.data(), n_geo * sizeof(double), hipMemcpyHostToDevice);
         }
-        if (rc) return cleanup(rc);
+        if (e != hipSuccess) return cleanup(fail(SDUGKS_EHIP, "upload of the face geometry failed"));
     }
     if (!tiled) {
         rc = upload_rows(h->at<int32_t>(L.off_nbr), mb.nbr, mb.D, nc, np, h->stream);
@@ -375,18 +382,18 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         h->dt.hdr = h->at<int32_t>(L.off_thdr);
         h->dt.lgid = h->at<int32_t>(L.off_lgid);
         h->dt.ladj = h->at<int16_t>(L.off_ladj);
-        h->dt.lw = dev ? nullptr : h->at<double>(L.off_lw);
-        h->dt.lw32 = dev ? h->at<float>(L.off_lw) : nullptr;
+        h->dt.lw = dev ? nullptr : h->at<double2>(L.off_lw);
+        h->dt.lw32 = dev ? h->at<float2>(L.off_lw) : nullptr;
     }
     DevMesh &d = h->dm;
-    d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces;
+    d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces; d.n_bc = (int32_t)mb.bcs.size();
     const size_t blk = (size_t)mb.D * np;
     if (dev) {
-        const float *g = h->at<float>(L.off_geo);
-        d.lnx32 = g; d.lny32 = g + blk; d.rsx32 = g + 2 * blk; d.rsy32 = g + 3 * blk; d.rox32 = g + 4 * blk; d.roy32 = g + 5 * blk;
+        const float2 *g = h->at<float2>(L.off_geo);
+        d.ln32 = g; d.rs32 = g + blk; d.ro32 = g + 2 * blk;
     } else {
-        const double *g = h->at<double>(L.off_geo);
-        d.lnx = g; d.lny = g + blk; d.rsx = g + 2 * blk; d.rsy = g + 3 * blk; d.rox = g + 4 * blk; d.roy = g + 5 * blk;
+        const double2 *g = h->at<double2>(L.off_geo);
+        d.ln = g; d.rs = g + blk; d.ro = g + 2 * blk;
     }
     if (!tiled) {
         d.nbr = h->at<int32_t>(L.off_nbr);
@@ -402,6 +409,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     d.b = dt / (2.0 * tau);
     d.c1 = 2.0 * tau / (2.0 * tau + dt);
     d.lam = dt / tau;
+    d.inv1l = 1.0 / (1.0 + d.lam);
     d.dt = dt;
     // initial state: uniform equilibrium, G = 0, snapshot = initial velocity
     {
@@ -668,7 +676,7 @@ int batch_build(sdugks_batch_t *b)
         if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->dev32 = dev; }
         g->members.push_back((int)k);
         g->block = std::max(g->block, h->block);
-        g->lds = std::max(g->lds, step_tiled_lds_bytes(h->dt, dev));
+        g->lds = std::max(g->lds, step_tiled_lds_bytes(h->dt, dev, (int)h->mb.bcs.size()));
         g->n_inst++;
         g->n_tiles += h->mb.n_tiles;
     }

@@ -15,19 +15,20 @@ struct DevBC {
 // Mesh and constants of one instance, as seen by the kernels.  All per-cell
 // arrays are pitched: entry (row r, cell c) at r*np + c.
 struct DevMesh {
-    int32_t nc, np, D, n_bfaces;
+    int32_t nc, np, D, n_bfaces, n_bc;
     const int32_t *nbr;                 // [D][np]
-    const double *lnx, *lny;            // [D][np] scaled outward normal
-    const double *rsx, *rsy;            // [D][np] midpoint - own centroid
-    const double *rox, *roy;            // [D][np] midpoint image - neighbour centroid
+    const double2 *ln;                  // [D][np] scaled outward normal (x, y)
+    const double2 *rs;                  // [D][np] midpoint - own centroid
+    const double2 *ro;                  // [D][np] midpoint image - neighbour centroid
     const double *ainv;                 // [3][np] inverse LSQ normal matrix
     const double *dtv;                  // [np] dt / V
     const double *area;                 // [np]
     const int32_t *bf_tag;              // [n_bfaces]
     const DevBC *bcs;                   // [n_bc]
     double a, b, c1, lam, dt;           // (2tau-dt)/2tau, dt/2tau, 2tau/(2tau+dt), dt/tau, dt
+    double inv1l;                       // 1 / (1 + dt/tau)
     // FP32 copies of the face geometry for the deviation form (null otherwise)
-    const float *lnx32, *lny32, *rsx32, *rsy32, *rox32, *roy32;
+    const float2 *ln32, *rs32, *ro32;
     double rho0;                        // offset of the deviation form: f = w_i rho0 + stored value
 };
 
@@ -41,15 +42,15 @@ struct DevState {
 };
 
 // Tiles of the fused step (see MeshBuild): headers [n_tiles][8] (g0, nt, n1,
-// n2), and the padded per-tile tables lgid [PL], ladj [D][PA], lw [D][2][PA]
-// with PL = nl_max, PA = na_max.
+// n2), and the padded per-tile tables lgid [PL], ladj [D][PA], lw [D][PA]
+// (x, y pairs) with PL = nl_max, PA = na_max.
 struct DevTiles {
     int32_t n_tiles, nl_max, na_max;
     const int32_t *hdr;
     const int32_t *lgid;
     const int16_t *ladj;
-    const double *lw;                   // FP64 form
-    const float *lw32;                  // deviation form
+    const double2 *lw;                  // FP64 form
+    const float2 *lw32;                 // deviation form
 };
 
 // One member of a batched launch: its mesh, tiles, both ping-pong buffers
@@ -82,7 +83,7 @@ hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScra
 // Fused one-kernel step over tiles (D <= 4 slots per cell).
 hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
                              int block, hipStream_t st);
-size_t step_tiled_lds_bytes(const DevTiles &t, int dev32);
+size_t step_tiled_lds_bytes(const DevTiles &t, int dev32, int n_bc);
 // Batched fused step over the tiles of all members (same D class and storage).
 hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity, int cap_tiles, size_t lds,
                              int block, hipStream_t st);

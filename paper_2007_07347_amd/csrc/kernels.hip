@@ -58,15 +58,15 @@ __global__ void __launch_bounds__(256) k_grad(DevMesh m, DevState s, DevScratch 
             const double rk = s.W[nb];
             const double uk = s.W[np + nb] / rk, vk = s.W[2 * np + nb] / rk;
             val = m.a * s.f[(size_t)i * np + nb] + m.b * feq_one(wi, exi, eyi, rk, uk, vk);
-            dx = m.rsx[q] - m.rox[q];
-            dy = m.rsy[q] - m.roy[q];
+            dx = m.rs[q].x - m.ro[q].x;
+            dy = m.rs[q].y - m.ro[q].y;
         } else {
             const DevBC bc = m.bcs[m.bf_tag[-1 - nb]];
             double rb, ub, vb;
             boundary_state(bc, rho, ux, uy, rb, ub, vb);
             val = feq_one(wi, exi, eyi, rb, ub, vb) + m.a * (fc - fe);
-            dx = m.rsx[q];
-            dy = m.rsy[q];
+            dx = m.rs[q].x;
+            dy = m.rs[q].y;
         }
         const double df = val - fb;
         ax += dx * df;
@@ -101,11 +101,13 @@ __global__ void __launch_bounds__(256) k_flux_update(DevMesh m, DevState s, DevS
     const int nb = (valid && sl < m.D) ? m.nbr[sl * np + c] : INT32_MIN;
     if (nb != INT32_MIN) {
         const int q = sl * np + c;
-        const double lnx = m.lnx[q], lny = m.lny[q];
-        const double rsx = m.rsx[q], rsy = m.rsy[q];
+        const double2 ln = m.ln[q], rsv = m.rs[q];
+        const double lnx = ln.x, lny = ln.y;
+        const double rsx = rsv.x, rsy = rsv.y;
         double fbar[9];
         if (nb >= 0) {
-            const double rox = m.rox[q], roy = m.roy[q];
+            const double2 rov = m.ro[q];
+            const double rox = rov.x, roy = rov.y;
 #pragma unroll
             for (int i = 0; i < 9; i++) {
                 const double sn = kEx[i] * lnx + kEy[i] * lny;
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(256) k_flux_update(DevMesh m, DevState s, DevS
         if (sl == 2 % L) s.Go[2 * np + c] = g2;
     }
     const double un = mxn / rn, vn = myn / rn;
-    const double inv = 1.0 / (1.0 + m.lam);
+    const double inv = m.inv1l;
 #pragma unroll
     for (int i = 0; i < 9; i++) {
         if (i % L != sl) continue;

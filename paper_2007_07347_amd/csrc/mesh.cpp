@@ -153,7 +153,7 @@ void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &p
     const size_t PL = out.nl_max, PA = out.na_max;
     out.lgid.assign((size_t)out.n_tiles * PL, 0);
     out.ladj.assign((size_t)out.n_tiles * D * PA, -1);
-    out.lw.assign((size_t)out.n_tiles * D * 2 * PA, 0.0);
+    out.lw.assign((size_t)out.n_tiles * D * PA * 2, 0.0);
     std::vector<int32_t> loc(nc, -1);
     for (int32_t t = 0; t < out.n_tiles; t++) {
         const std::vector<int32_t> &L = locals[t];
@@ -169,8 +169,8 @@ void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &p
                 else if (nb < 0) v = (int16_t)(-2 - out.bf_tag[-1 - nb]);
                 else v = (int16_t)loc[nb];
                 out.ladj[((size_t)t * D + s) * PA + k] = v;
-                out.lw[(((size_t)t * D + s) * 2 + 0) * PA + k] = out.wx[q];
-                out.lw[(((size_t)t * D + s) * 2 + 1) * PA + k] = out.wy[q];
+                out.lw[(((size_t)t * D + s) * PA + k) * 2 + 0] = out.wx[q];
+                out.lw[(((size_t)t * D + s) * PA + k) * 2 + 1] = out.wy[q];
             }
         }
         for (int32_t c : L) loc[c] = -1;
@@ -328,7 +328,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
 
     // ---- cell order: tile-major (fused step) or reverse Cuthill-McKee
     std::vector<int32_t> perm(nc), iperm(nc);
-    const bool tiled = prm->tile_cells >= 0 && D <= 4;
+    const bool tiled = prm->tile_cells >= 0 && D <= 4 && n_bc <= kMaxTileBcs;
     const int32_t B = prm->block_threads > 0 ? prm->block_threads : kDefaultBlock;
     int32_t T = prm->tile_cells > 0 ? std::min(prm->tile_cells, B / 4) : B / 4;
     if (tiled && T < 4) BAD("tile_cells must be at least 4 (or 0 / -1)");
@@ -431,7 +431,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lw.clear();
     if (tiled) {
         build_tiles(out, parts);
-        if (tile_lds_bytes(out.nl_max, out.na_max) > kTileLdsLimit || out.nl_max > B) {
+        if (tile_lds_bytes(out.nl_max, out.na_max, n_bc) > kTileLdsLimit || out.nl_max > B) {
             // one thread per local cell and LDS for all of them: bisect into smaller tiles
             if (T <= 4) BAD("mesh too irregular for the fused step's tiles");
             sdugks_params smaller = *prm;

@@ -49,7 +49,7 @@ struct MeshBuild {
     //   ladj [n_tiles][D][PA]       neighbour behind each slot of a tile or
     //                               first-ring cell: local index >= 0, -1 empty,
     //                               -2 - tag for a boundary face of that tag;
-    //   lw   [n_tiles][D][2][PA]    its least-squares weight (x, y).
+    //   lw   [n_tiles][D][PA][2]    its least-squares weight (x, y).
     int32_t tile_T = 0, n_tiles = 0, nl_max = 0, na_max = 0;
     std::vector<int32_t> tile_hdr;   // [n_tiles][8]: g0, nt, n1, n2, 0...
     std::vector<int32_t> lgid;
@@ -57,8 +57,16 @@ struct MeshBuild {
     std::vector<double> lw;
 };
 
-// LDS bytes of one workgroup of the fused FP64 step for the given maxima.
-inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max) { return (14 * (size_t)nl_max + 18 * (size_t)na_max) * 8; }
+// Boundary-condition entries the fused step keeps in LDS (more: two-kernel step).
+constexpr int32_t kMaxTileBcs = 64;
+// LDS bytes of one workgroup of the fused step: per local cell W, u and fbar+,
+// per tile or first-ring cell the gradient (elem bytes: 8 FP64, 4 deviation
+// form), then the boundary-condition table (4 doubles per entry).
+inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max, int32_t n_bc, size_t elem = 8)
+{
+    const size_t head = 5 * (size_t)nl_max * 8 + (9 * (size_t)nl_max + 18 * (size_t)na_max) * elem;
+    return (head + 15) / 16 * 16 + 32 * (size_t)n_bc;
+}
 constexpr size_t kTileLdsLimit = 64 * 1024;
 constexpr int32_t kDefaultBlock = 256;   // threads of the fused step; tiles hold at most a quarter as many cells
 

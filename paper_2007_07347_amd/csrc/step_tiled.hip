@@ -32,6 +32,7 @@
 
 #include "d2q9.h"
 #include "device.h"
+#include "mesh.h"
 
 namespace sdg {
 
@@ -62,12 +63,15 @@ __device__ __forceinline__ float lane_sum4_comp(float v)
     return v + e;
 }
 
-__device__ __forceinline__ void boundary_state_t(const DevBC &bc, double rho, double ux, double uy,
+// Boundary state of entry e of the LDS table (type, rho, u, v) seen from a
+// cell with macros (rho, ux, uy).
+__device__ __forceinline__ void boundary_state_t(const double *sbc, int e, double rho, double ux, double uy,
                                                  double &rb, double &ub, double &vb)
 {
-    if (bc.type == 2) { rb = bc.rho; ub = bc.u; vb = bc.v; }          // inlet / far field
-    else if (bc.type == 3) { rb = rho; ub = ux; vb = uy; }            // outlet
-    else { rb = rho; ub = bc.u; vb = bc.v; }                          // wall
+    const double type = sbc[4 * e], brho = sbc[4 * e + 1], bu = sbc[4 * e + 2], bv = sbc[4 * e + 3];
+    if (type == 2.0) { rb = brho; ub = bu; vb = bv; }                // inlet / far field
+    else if (type == 3.0) { rb = rho; ub = ux; vb = uy; }            // outlet
+    else { rb = rho; ub = bu; vb = bv; }                             // wall
 }
 
 // D2Q9 constants of a lane-dependent velocity index i.
@@ -89,65 +93,72 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     double *sW = smem;                                        // [5][P]: rho, rho u, rho v, u, v
     R *sfbp = reinterpret_cast<R *>(smem + 5 * P);            // [9][P] fbar+ (deviation in DEV)
     R *ssg = sfbp + 9 * P;                                    // [18][P1] gradient (x rows 0..8, y rows 9..17)
+    // boundary-condition table [n_bc][4]: type, rho, u, v (16-byte aligned after the gradient)
+    double *sbc = smem + ((5 * P * 8 + (9 * P + 18 * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
-    const R *lw;
-    const R *glnx, *glny, *grsx, *grsy, *grox, *groy;
+    using R2 = typename std::conditional<DEV, float2, double2>::type;
+    const R2 *lw, *gln, *grs, *gro;
     if constexpr (DEV) {
-        lw = tl.lw32 + (size_t)t * D * 2 * P1;
-        glnx = m.lnx32; glny = m.lny32; grsx = m.rsx32; grsy = m.rsy32; grox = m.rox32; groy = m.roy32;
+        lw = tl.lw32 + (size_t)t * D * P1;
+        gln = m.ln32; grs = m.rs32; gro = m.ro32;
     } else {
-        lw = tl.lw + (size_t)t * D * 2 * P1;
-        glnx = m.lnx; glny = m.lny; grsx = m.rsx; grsy = m.rsy; grox = m.rox; groy = m.roy;
+        lw = tl.lw + (size_t)t * D * P1;
+        gln = m.ln; grs = m.rs; gro = m.ro;
     }
     const R ra = (R)m.a, rb_ = (R)m.b, rc1 = (R)m.c1, rdt = (R)m.dt;
     // constant part of f removed in the deviation form
     auto off = [&](int i) { return DEV ? kW[i] * m.rho0 : 0.0; };
 
-    // ---- requests of all phases
+    // ---- requests of all phases, in this order: the local cell ids; the
+    // inputs of phases 2 and 3 (adjacency, weights, face geometry, boundary
+    // table), which need nothing loaded first; then the phase-1 state at the
+    // cell ids.  Loads are unconditional at clamped (valid) indices, lanes
+    // without work ignore what they read (padded cell ids are 0, a valid cell).
     const bool p1 = tid < nl;
-    const int g1 = p1 ? tl.lgid[(size_t)t * P + tid] : 0;
+    const unsigned g1 = (unsigned)tl.lgid[(size_t)t * P + (p1 ? tid : 0)];
+    __builtin_amdgcn_sched_barrier(0);
     const bool p2 = tid < na;
+    const int t2 = p2 ? tid : 0;
     int la2[D];
     R wx2[D], wy2[D];
 #pragma unroll
     for (int sl = 0; sl < D; sl++) {
-        la2[sl] = p2 ? ladj[sl * P1 + tid] : -1;
-        wx2[sl] = p2 ? lw[(2 * sl) * P1 + tid] : (R)0;
-        wy2[sl] = p2 ? lw[(2 * sl + 1) * P1 + tid] : (R)0;
+        const int a = ladj[sl * P1 + t2];
+        la2[sl] = p2 ? a : -1;
+        const R2 w = lw[sl * P1 + t2];
+        wx2[sl] = w.x;
+        wy2[sl] = w.y;
     }
     const int lc3 = tid >> 2, sl3 = tid & 3;
     const bool p3 = lc3 < nt;
-    const int g3 = g0 + lc3;
-    const int la3 = (p3 && sl3 < D) ? ladj[sl3 * P1 + lc3] : -1;
-    const int q3 = sl3 * np + g3;
-    R lnx = 0, lny = 0, rsx = 0, rsy = 0, rox = 0, roy = 0;
-    if (la3 != -1) { lnx = glnx[q3]; lny = glny[q3]; rsx = grsx[q3]; rsy = grsy[q3]; }
-    if (la3 >= 0) { rox = grox[q3]; roy = groy[q3]; }
-    // the lane's velocities in the update: sl3, sl3 + 4 and, on lane 0, 8
-    double fo0 = 0.0, fo1 = 0.0, fo2 = 0.0, dtv = 0.0;
-    if (p3) {
-        if constexpr (DEV) {
-            fo0 = s.f32[(size_t)sl3 * np + g3];
-            fo1 = s.f32[(size_t)(sl3 + 4) * np + g3];
-            if (sl3 == 0) fo2 = s.f32[(size_t)8 * np + g3];
-        } else {
-            fo0 = s.f[(size_t)sl3 * np + g3];
-            fo1 = s.f[(size_t)(sl3 + 4) * np + g3];
-            if (sl3 == 0) fo2 = s.f[(size_t)8 * np + g3];
-        }
-        dtv = m.dtv[g3];
+    const int g3 = g0 + (p3 ? lc3 : 0);
+    const int sl3c = sl3 < D ? sl3 : D - 1;
+    const int a3 = ladj[sl3c * P1 + (p3 ? lc3 : 0)];
+    const int la3 = (p3 && sl3 < D) ? a3 : -1;
+    const int q3 = sl3c * np + g3;
+    const R2 lnv = gln[q3], rsv = grs[q3], rov = gro[q3];
+    const R lnx = lnv.x, lny = lnv.y, rsx = rsv.x, rsy = rsv.y, rox = rov.x, roy = rov.y;
+    const bool pb = tid < m.n_bc;
+    const DevBC bcl = m.bcs[pb ? tid : 0];
+    __builtin_amdgcn_sched_barrier(0);
+    const double r = s.W[g1], mu = s.W[(size_t)np + g1], mv = s.W[2 * (size_t)np + g1];
+    R fv[9];
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        if constexpr (DEV) fv[i] = s.f32[(size_t)i * np + g1];
+        else fv[i] = s.f[(size_t)i * np + g1];
     }
 
     // ---- phase 1: macros and fbar+ of every local cell
+    if (pb) {
+        sbc[4 * tid] = (double)bcl.type;
+        sbc[4 * tid + 1] = bcl.rho;
+        sbc[4 * tid + 2] = bcl.u;
+        sbc[4 * tid + 3] = bcl.v;
+    }
     if (p1) {
-        const double r = s.W[g1], mu = s.W[np + g1], mv = s.W[2 * np + g1];
-        R fv[9];
-#pragma unroll
-        for (int i = 0; i < 9; i++) {
-            if constexpr (DEV) fv[i] = s.f32[(size_t)i * np + g1];
-            else fv[i] = s.f[(size_t)i * np + g1];
-        }
-        const double ux = mu / r, uy = mv / r;
+        const double ir = 1.0 / r;
+        const double ux = mu * ir, uy = mv * ir;
         sW[tid] = r;
         sW[P + tid] = mu;
         sW[2 * P + tid] = mv;
@@ -177,10 +188,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
                 }
             } else {
                 // boundary point: fbar+_b - fbar+_c = feq(rho_b, u_b) - feq(W_c)
-                const DevBC bc = m.bcs[-2 - la];
                 const double r = sW[tid], ux = sW[3 * P + tid], uy = sW[4 * P + tid];
                 double rb, ub, vb;
-                boundary_state_t(bc, r, ux, uy, rb, ub, vb);
+                boundary_state_t(sbc, -2 - la, r, ux, uy, rb, ub, vb);
 #pragma unroll
                 for (int i = 0; i < 9; i++) {
                     const R df = (R)(feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy));
@@ -198,6 +208,19 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     __syncthreads();
 
     // ---- phase 3: the face of each lane, per-cell sums, update
+    // the lane's velocities in the update: sl3, sl3 + 4 and, on lane 0, 8
+    // (the tile's own cells, just read in phase 1: cache hits)
+    double fo0, fo1, fo2;
+    if constexpr (DEV) {
+        fo0 = s.f32[(size_t)sl3 * np + g3];
+        fo1 = s.f32[(size_t)(sl3 + 4) * np + g3];
+        fo2 = s.f32[(size_t)8 * np + g3];
+    } else {
+        fo0 = s.f[(size_t)sl3 * np + g3];
+        fo1 = s.f[(size_t)(sl3 + 4) * np + g3];
+        fo2 = s.f[(size_t)8 * np + g3];
+    }
+    const double dtv = m.dtv[g3];
     R phi[9];
     double g0s = 0.0, g1s = 0.0, g2s = 0.0;
 #pragma unroll
@@ -218,10 +241,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
                 fbar[i] = sn > (R)0 ? rs : (sn < (R)0 ? ro : (R)0.5 * (rs + ro));
             }
         } else {
-            const DevBC bc = m.bcs[-2 - la3];
             const double r = sW[lc], ux = sW[3 * P + lc], uy = sW[4 * P + lc];
             double rb, ub, vb;
-            boundary_state_t(bc, r, ux, uy, rb, ub, vb);
+            boundary_state_t(sbc, -2 - la3, r, ux, uy, rb, ub, vb);
 #pragma unroll
             for (int i = 0; i < 9; i++) {
                 const R ex = (R)kEx[i], ey = (R)kEy[i];
@@ -239,7 +261,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
 #pragma unroll
         for (int i = 0; i < 9; i++) { rsum += fbar[i]; mx += (R)kEx[i] * fbar[i]; my += (R)kEy[i] * fbar[i]; }
         const R rf = DEV ? (R)m.rho0 + rsum : rsum;
-        const R uf = mx / rf, vf = my / rf;
+        const R irf = (R)1 / rf;
+        const R uf = mx * irf, vf = my * irf;
         const R uu = uf * uf + vf * vf;
 #pragma unroll
         for (int i = 0; i < 9; i++) {
@@ -281,8 +304,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             if (sl3 == 1) s.Go[np + g] = g1s;
             if (sl3 == 2) s.Go[2 * np + g] = g2s;
         }
-        const double un = mxn / rn, vn = myn / rn;
-        const double inv = 1.0 / (1.0 + m.lam);
+        const double irn = 1.0 / rn;
+        const double un = mxn * irn, vn = myn * irn;
+        const double inv = m.inv1l;
         // this lane's velocities and their fluxes
         const int i0 = sl3, i1 = sl3 + 4;
         const double F0 = sl3 == 0 ? phi[0] : (sl3 == 1 ? phi[1] : (sl3 == 2 ? phi[2] : phi[3]));
@@ -348,10 +372,9 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
 
 }  // namespace
 
-size_t step_tiled_lds_bytes(const DevTiles &t, int dev32)
+size_t step_tiled_lds_bytes(const DevTiles &t, int dev32, int n_bc)
 {
-    const size_t r = dev32 ? sizeof(float) : sizeof(double);
-    return 5 * (size_t)t.nl_max * sizeof(double) + (9 * (size_t)t.nl_max + 18 * (size_t)t.na_max) * r;
+    return tile_lds_bytes(t.nl_max, t.na_max, n_bc, dev32 ? sizeof(float) : sizeof(double));
 }
 
 static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)((t.n_tiles + kXcds - 1) / kXcds * kXcds); }
@@ -359,7 +382,7 @@ static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)((t.n_tile
 hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
                              int block, hipStream_t st)
 {
-    const size_t lds = step_tiled_lds_bytes(t, dev32);
+    const size_t lds = step_tiled_lds_bytes(t, dev32, m.n_bc);
     const dim3 grid(step_tiled_grid(t)), blk(block);
     if (m.D <= 3) {
         if (dev32) hipLaunchKernelGGL((k_step_tiled<3, true>), grid, blk, lds, st, m, t, s, lagged);
