@@ -12,6 +12,10 @@ SOURCES = ["api.cpp", "mesh.cpp", "kernels.hip", "step_tiled.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              # packed FP32 instructions are kept out of every kernel
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # multiply-adds are fused per source expression (front end), not by
+             # backend heuristics that depend on the surrounding code: kernels
+             # that inline the same step compute bit-identical results
+             "-ffp-contract=on",
              "-Wall", "-Wno-unused-function"]
 
 

@@ -29,6 +29,7 @@
 // two tiles is evaluated by both from identical operands: the flux that
 // leaves one cell enters the other exactly.
 #include <type_traits>
+#include <utility>
 
 #include "d2q9.h"
 #include "device.h"
@@ -38,10 +39,81 @@ namespace sdg {
 
 namespace {
 
+// ---- compile-time lattice arithmetic.  Velocity loops are unrolled with the
+// index as a constant, so products with the lattice components 0 and +-1
+// are written as what they are (IEEE rules forbid the compiler to drop
+// x * 0 on its own).
+constexpr int cEx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int cEy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr double cW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// c x for c in {-1, 0, 1}
+template <int C, typename T>
+__device__ __forceinline__ T cmul(T x)
+{
+    if constexpr (C == 0) return T(0);
+    else if constexpr (C > 0) return x;
+    else return -x;
+}
+// a x + b y for a, b in {-1, 0, 1}, one rounding at most
+template <int A, int B, typename T>
+__device__ __forceinline__ T cdot(T x, T y)
+{
+    if constexpr (A == 0) return cmul<B>(y);
+    else if constexpr (B == 0) return cmul<A>(x);
+    else if constexpr (A > 0 && B > 0) return x + y;
+    else if constexpr (A > 0) return x - y;
+    else if constexpr (B > 0) return y - x;
+    else return -(x + y);
+}
+// x - c d for c in {-1, 0, 1}
+template <int C, typename T>
+__device__ __forceinline__ T csub(T x, T d)
+{
+    if constexpr (C == 0) return x;
+    else if constexpr (C > 0) return x - d;
+    else return x + d;
+}
+// Second-order equilibrium of velocity (EX, EY) with weight w, uu = u.u.
+template <int EX, int EY, typename T>
+__device__ __forceinline__ T feq_c(T w, T rho, T ux, T uy, T uu)
+{
+    const T eu = cdot<EX, EY>(ux, uy);
+    return w * rho * ((T)1 + (T)3 * eu + (T)4.5 * eu * eu - (T)1.5 * uu);
+}
+
+// Quad-lane exchange by DPP (no LDS traffic): lane l reads lane l ^ 1 (0xB1)
+// or l ^ 2 (0x4E) of its group of four.
+template <int CTRL>
+__device__ __forceinline__ double qx(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ float qx(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over the four lanes of a cell, butterfly order: (a + b) + (c + d) on
+// every lane, so all four end with the same bits.
 __device__ __forceinline__ double lane_sum4(double v)
 {
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
+    v += qx<0xB1>(v);
+    v += qx<0x4E>(v);
     return v;
 }
 
@@ -51,15 +123,15 @@ __device__ __forceinline__ double lane_sum4(double v)
 __device__ __forceinline__ float lane_sum4_comp(float v)
 {
     float e = 0.0f;
-#pragma unroll
-    for (int off = 1; off < 4; off <<= 1) {
-        const float b = __shfl_xor(v, off, 64), eb = __shfl_xor(e, off, 64);
+    static_for<2>([&](auto L) {
+        constexpr int CTRL = L == 0 ? 0xB1 : 0x4E;
+        const float b = qx<CTRL>(v), eb = qx<CTRL>(e);
         const float sum = v + b;
         const float bb = sum - v;
         const float err = (v - (sum - bb)) + (b - bb);
         e = (e + eb) + err;
         v = sum;
-    }
+    });
     return v + e;
 }
 
@@ -74,10 +146,6 @@ __device__ __forceinline__ void boundary_state_t(const double *sbc, int e, doubl
     else { rb = rho; ub = bu; vb = bv; }                             // wall
 }
 
-// D2Q9 constants of a lane-dependent velocity index i.
-__device__ __forceinline__ double ex_rt(int i) { return (double)((0x20919 >> (2 * i) & 3) - 1); }
-__device__ __forceinline__ double ey_rt(int i) { return (double)((0x02865 >> (2 * i) & 3) - 1); }
-__device__ __forceinline__ double w_rt(int i) { return i == 0 ? 4.0 / 9 : (i < 5 ? 1.0 / 9 : 1.0 / 36); }
 
 // One time step of tile t of one instance (the whole workgroup takes part).
 template <int D, bool DEV>
@@ -106,9 +174,6 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         gln = m.ln; grs = m.rs; gro = m.ro;
     }
     const R ra = (R)m.a, rb_ = (R)m.b, rc1 = (R)m.c1, rdt = (R)m.dt;
-    // constant part of f removed in the deviation form
-    auto off = [&](int i) { return DEV ? kW[i] * m.rho0 : 0.0; };
-
     // ---- requests of all phases, in this order: the local cell ids; the
     // inputs of phases 2 and 3 (adjacency, weights, face geometry, boundary
     // table), which need nothing loaded first; then the phase-1 state at the
@@ -158,15 +223,17 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     }
     if (p1) {
         const double ir = 1.0 / r;
-        const double ux = mu * ir, uy = mv * ir;
+        const double ux = mu * ir, uy = mv * ir, uu = ux * ux + uy * uy;
         sW[tid] = r;
         sW[P + tid] = mu;
         sW[2 * P + tid] = mv;
         sW[3 * P + tid] = ux;
         sW[4 * P + tid] = uy;
-#pragma unroll
-        for (int i = 0; i < 9; i++)
-            sfbp[i * P + tid] = ra * fv[i] + rb_ * (R)(feq_one(kW[i], kEx[i], kEy[i], r, ux, uy) - off(i));
+        static_for<9>([&](auto I) {
+            constexpr int i = I;
+            const double fe = feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu) - (DEV ? cW[i] * m.rho0 : 0.0);
+            sfbp[i * P + tid] = ra * fv[i] + rb_ * (R)fe;
+        });
     }
     __syncthreads();
 
@@ -191,12 +258,14 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
                 const double r = sW[tid], ux = sW[3 * P + tid], uy = sW[4 * P + tid];
                 double rb, ub, vb;
                 boundary_state_t(sbc, -2 - la, r, ux, uy, rb, ub, vb);
-#pragma unroll
-                for (int i = 0; i < 9; i++) {
-                    const R df = (R)(feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy));
+                const double uu = ux * ux + uy * uy, uub = ub * ub + vb * vb;
+                static_for<9>([&](auto I) {
+                    constexpr int i = I;
+                    const R df = (R)(feq_c<cEx[i], cEy[i]>(cW[i], rb, ub, vb, uub) -
+                                     feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu));
                     ax[i] += wx2[sl] * df;
                     ay[i] += wy2[sl] * df;
-                }
+                });
             }
         }
 #pragma unroll
@@ -229,57 +298,61 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         const int lc = lc3;
         R fbar[9];
         if (la3 >= 0) {
+            // upwind side by the sign of e.n; exact tie: mean of both sides
             const int la = la3;
-#pragma unroll
-            for (int i = 0; i < 9; i++) {
-                const R ex = (R)kEx[i], ey = (R)kEy[i];
-                const R sn = ex * lnx + ey * lny;
-                const R rs = sfbp[i * P + lc] + (rsx - rdt * ex) * ssg[i * P1 + lc]
-                             + (rsy - rdt * ey) * ssg[(9 + i) * P1 + lc];
-                const R ro = sfbp[i * P + la] + (rox - rdt * ex) * ssg[i * P1 + la]
-                             + (roy - rdt * ey) * ssg[(9 + i) * P1 + la];
-                fbar[i] = sn > (R)0 ? rs : (sn < (R)0 ? ro : (R)0.5 * (rs + ro));
-            }
+            static_for<9>([&](auto I) {
+                constexpr int i = I, EX = cEx[i], EY = cEy[i];
+                const R sn = cdot<EX, EY>(lnx, lny);
+                const R rs = sfbp[i * P + lc] + csub<EX>(rsx, rdt) * ssg[i * P1 + lc]
+                             + csub<EY>(rsy, rdt) * ssg[(9 + i) * P1 + lc];
+                const R ro = sfbp[i * P + la] + csub<EX>(rox, rdt) * ssg[i * P1 + la]
+                             + csub<EY>(roy, rdt) * ssg[(9 + i) * P1 + la];
+                const R up = sn > (R)0 ? rs : ro;
+                fbar[i] = sn == (R)0 ? (R)0.5 * (rs + ro) : up;
+            });
         } else {
             const double r = sW[lc], ux = sW[3 * P + lc], uy = sW[4 * P + lc];
             double rb, ub, vb;
             boundary_state_t(sbc, -2 - la3, r, ux, uy, rb, ub, vb);
-#pragma unroll
-            for (int i = 0; i < 9; i++) {
-                const R ex = (R)kEx[i], ey = (R)kEy[i];
-                const R sn = ex * lnx + ey * lny;
+            const double uu = ux * ux + uy * uy, uub = ub * ub + vb * vb;
+            static_for<9>([&](auto I) {
+                constexpr int i = I, EX = cEx[i], EY = cEy[i];
+                const R sn = cdot<EX, EY>(lnx, lny);
                 const R sx = ssg[i * P1 + lc], sy = ssg[(9 + i) * P1 + lc];
                 const R fb = sfbp[i * P + lc];
-                const R inner = fb + (rsx - rdt * ex) * sx + (rsy - rdt * ey) * sy;
+                const R inner = fb + csub<EX>(rsx, rdt) * sx + csub<EY>(rsy, rdt) * sy;
                 // incoming: the boundary state's fbar+ carried to the foot point
-                const R gb = (R)(feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - feq_one(kW[i], kEx[i], kEy[i], r, ux, uy)) + fb;
-                fbar[i] = sn >= (R)0 ? inner : gb - rdt * (ex * sx + ey * sy);
-            }
+                const R gb = (R)(feq_c<EX, EY>(cW[i], rb, ub, vb, uub) - feq_c<EX, EY>(cW[i], r, ux, uy, uu)) + fb;
+                fbar[i] = sn >= (R)0 ? inner : gb - rdt * cdot<EX, EY>(sx, sy);
+            });
         }
         // face macros (deviations in DEV: rho_f = rho0 + sum, momentum unchanged)
-        R rsum = 0, mx = 0, my = 0;
-#pragma unroll
-        for (int i = 0; i < 9; i++) { rsum += fbar[i]; mx += (R)kEx[i] * fbar[i]; my += (R)kEy[i] * fbar[i]; }
+        R rsum = fbar[0], mx = 0, my = 0;
+        static_for<9>([&](auto I) {
+            constexpr int i = I;
+            if constexpr (i > 0) rsum += fbar[i];
+            if constexpr (cEx[i] != 0) mx += cmul<cEx[i]>(fbar[i]);
+            if constexpr (cEy[i] != 0) my += cmul<cEy[i]>(fbar[i]);
+        });
         const R rf = DEV ? (R)m.rho0 + rsum : rsum;
         const R irf = (R)1 / rf;
         const R uf = mx * irf, vf = my * irf;
         const R uu = uf * uf + vf * vf;
-#pragma unroll
-        for (int i = 0; i < 9; i++) {
-            const R ex = (R)kEx[i], ey = (R)kEy[i];
-            const R sn = ex * lnx + ey * lny;
+        static_for<9>([&](auto I) {
+            constexpr int i = I, EX = cEx[i], EY = cEy[i];
+            const R sn = cdot<EX, EY>(lnx, lny);
             R fe;
             if constexpr (DEV) {
-                const R eu = ex * uf + ey * vf;
-                fe = (R)kW[i] * (rsum + rf * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * uu));
+                const R eu = cdot<EX, EY>(uf, vf);
+                fe = (R)cW[i] * (rsum + rf * ((R)3 * eu + (R)4.5 * eu * eu - (R)1.5 * uu));
             } else {
-                fe = feq_one(kW[i], kEx[i], kEy[i], rf, uf, vf);
+                fe = feq_c<EX, EY>((R)cW[i], rf, uf, vf, uu);
             }
             phi[i] = sn * (rc1 * (fbar[i] + rb_ * fe));
             g0s += (double)phi[i];
-            g1s += kEx[i] * (double)phi[i];
-            g2s += kEy[i] * (double)phi[i];
-        }
+            if constexpr (EX != 0) g1s += cmul<EX>((double)phi[i]);
+            if constexpr (EY != 0) g2s += cmul<EY>((double)phi[i]);
+        });
     }
 #pragma unroll
     for (int i = 0; i < 9; i++) {
@@ -305,21 +378,25 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             if (sl3 == 2) s.Go[2 * np + g] = g2s;
         }
         const double irn = 1.0 / rn;
-        const double un = mxn * irn, vn = myn * irn;
-        const double inv = m.inv1l;
-        // this lane's velocities and their fluxes
-        const int i0 = sl3, i1 = sl3 + 4;
+        const double un = mxn * irn, vn = myn * irn, uun = un * un + vn * vn;
+        const double inv = m.inv1l, lam = m.lam;
+        // this lane's velocities: i0 = sl3 (rest, +x, +y, -x) and i1 = sl3 + 4
+        // (-y, (1,1), (-1,1), (-1,-1)); their e.u, weights and fluxes
+        const double eu0 = sl3 == 0 ? 0.0 : (sl3 == 1 ? un : (sl3 == 2 ? vn : -un));
+        const double eu1 = sl3 == 0 ? -vn : (sl3 == 1 ? un + vn : (sl3 == 2 ? vn - un : -(un + vn)));
+        const double w0 = sl3 == 0 ? cW[0] : cW[1], w1 = sl3 == 0 ? cW[4] : cW[5];
         const double F0 = sl3 == 0 ? phi[0] : (sl3 == 1 ? phi[1] : (sl3 == 2 ? phi[2] : phi[3]));
         const double F1 = sl3 == 0 ? phi[4] : (sl3 == 1 ? phi[5] : (sl3 == 2 ? phi[6] : phi[7]));
-        const double o0 = DEV ? w_rt(i0) * m.rho0 : 0.0, o1 = DEV ? w_rt(i1) * m.rho0 : 0.0;
-        const double fe0 = feq_one(w_rt(i0), ex_rt(i0), ey_rt(i0), rn, un, vn) - o0;
-        const double fe1 = feq_one(w_rt(i1), ex_rt(i1), ey_rt(i1), rn, un, vn) - o1;
-        const double v0 = (fo0 - dtv * F0 + m.lam * fe0) * inv, v1 = (fo1 - dtv * F1 + m.lam * fe1) * inv;
+        const double base = 1.0 - 1.5 * uun;
+        const double fe0 = w0 * rn * (base + eu0 * (3.0 + 4.5 * eu0)) - (DEV ? w0 * m.rho0 : 0.0);
+        const double fe1 = w1 * rn * (base + eu1 * (3.0 + 4.5 * eu1)) - (DEV ? w1 * m.rho0 : 0.0);
+        const double v0 = (fo0 - dtv * F0 + lam * fe0) * inv, v1 = (fo1 - dtv * F1 + lam * fe1) * inv;
+        const int i0 = sl3, i1 = sl3 + 4;
         if constexpr (DEV) { s.fo32[(size_t)i0 * np + g] = (float)v0; s.fo32[(size_t)i1 * np + g] = (float)v1; }
         else { s.fo[(size_t)i0 * np + g] = v0; s.fo[(size_t)i1 * np + g] = v1; }
         if (sl3 == 0) {
-            const double fe2 = feq_one(kW[8], kEx[8], kEy[8], rn, un, vn) - off(8);
-            const double v2 = (fo2 - dtv * (double)phi[8] + m.lam * fe2) * inv;
+            const double fe2 = feq_c<cEx[8], cEy[8]>(cW[8], rn, un, vn, uun) - (DEV ? cW[8] * m.rho0 : 0.0);
+            const double v2 = (fo2 - dtv * (double)phi[8] + lam * fe2) * inv;
             if constexpr (DEV) s.fo32[(size_t)8 * np + g] = (float)v2;
             else s.fo[(size_t)8 * np + g] = v2;
         }
