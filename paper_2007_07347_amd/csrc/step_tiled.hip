@@ -159,8 +159,11 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     const int np = m.np;
     const int tid = threadIdx.x;
     double *sW = smem;                                        // [5][P]: rho, rho u, rho v, u, v
-    R *sfbp = reinterpret_cast<R *>(smem + 5 * P);            // [9][P] fbar+ (deviation in DEV)
-    R *ssg = sfbp + 9 * P;                                    // [18][P1] gradient (x rows 0..8, y rows 9..17)
+    // per cell: fbar+ [P][9] (deviation in DEV) and its gradient [P1][18]
+    // (x components 0..8, y components 9..17); cell-major, so the velocity
+    // and component are constant offsets of one per-cell address
+    R *sfbp = reinterpret_cast<R *>(smem + 5 * P);
+    R *ssg = sfbp + 9 * P;
     // boundary-condition table [n_bc][4]: type, rho, u, v (16-byte aligned after the gradient)
     double *sbc = smem + ((5 * P * 8 + (9 * P + 18 * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
@@ -232,7 +235,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         static_for<9>([&](auto I) {
             constexpr int i = I;
             const double fe = feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu) - (DEV ? cW[i] * m.rho0 : 0.0);
-            sfbp[i * P + tid] = ra * fv[i] + rb_ * (R)fe;
+            sfbp[tid * 9 + i] = ra * fv[i] + rb_ * (R)fe;
         });
     }
     __syncthreads();
@@ -241,7 +244,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     if (p2) {
         R ax[9], ay[9], fc[9];
 #pragma unroll
-        for (int i = 0; i < 9; i++) { ax[i] = 0; ay[i] = 0; fc[i] = sfbp[i * P + tid]; }
+        for (int i = 0; i < 9; i++) { ax[i] = 0; ay[i] = 0; fc[i] = sfbp[tid * 9 + i]; }
 #pragma unroll
         for (int sl = 0; sl < D; sl++) {
             const int la = la2[sl];
@@ -249,7 +252,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             if (la >= 0) {
 #pragma unroll
                 for (int i = 0; i < 9; i++) {
-                    const R df = sfbp[i * P + la] - fc[i];
+                    const R df = sfbp[la * 9 + i] - fc[i];
                     ax[i] += wx2[sl] * df;
                     ay[i] += wy2[sl] * df;
                 }
@@ -270,8 +273,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         }
 #pragma unroll
         for (int i = 0; i < 9; i++) {
-            ssg[i * P1 + tid] = ax[i];
-            ssg[(9 + i) * P1 + tid] = ay[i];
+            ssg[tid * 18 + i] = ax[i];
+            ssg[tid * 18 + 9 + i] = ay[i];
         }
     }
     __syncthreads();
@@ -303,10 +306,10 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             static_for<9>([&](auto I) {
                 constexpr int i = I, EX = cEx[i], EY = cEy[i];
                 const R sn = cdot<EX, EY>(lnx, lny);
-                const R rs = sfbp[i * P + lc] + csub<EX>(rsx, rdt) * ssg[i * P1 + lc]
-                             + csub<EY>(rsy, rdt) * ssg[(9 + i) * P1 + lc];
-                const R ro = sfbp[i * P + la] + csub<EX>(rox, rdt) * ssg[i * P1 + la]
-                             + csub<EY>(roy, rdt) * ssg[(9 + i) * P1 + la];
+                const R rs = sfbp[lc * 9 + i] + csub<EX>(rsx, rdt) * ssg[lc * 18 + i]
+                             + csub<EY>(rsy, rdt) * ssg[lc * 18 + 9 + i];
+                const R ro = sfbp[la * 9 + i] + csub<EX>(rox, rdt) * ssg[la * 18 + i]
+                             + csub<EY>(roy, rdt) * ssg[la * 18 + 9 + i];
                 const R up = sn > (R)0 ? rs : ro;
                 fbar[i] = sn == (R)0 ? (R)0.5 * (rs + ro) : up;
             });
@@ -318,8 +321,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             static_for<9>([&](auto I) {
                 constexpr int i = I, EX = cEx[i], EY = cEy[i];
                 const R sn = cdot<EX, EY>(lnx, lny);
-                const R sx = ssg[i * P1 + lc], sy = ssg[(9 + i) * P1 + lc];
-                const R fb = sfbp[i * P + lc];
+                const R sx = ssg[lc * 18 + i], sy = ssg[lc * 18 + 9 + i];
+                const R fb = sfbp[lc * 9 + i];
                 const R inner = fb + csub<EX>(rsx, rdt) * sx + csub<EY>(rsy, rdt) * sy;
                 // incoming: the boundary state's fbar+ carried to the foot point
                 const R gb = (R)(feq_c<EX, EY>(cW[i], rb, ub, vb, uub) - feq_c<EX, EY>(cW[i], r, ux, uy, uu)) + fb;
