@@ -153,6 +153,7 @@ class Solver:
 
     def __init__(self, mesh, bcs, stream=None, **kw):
         import torch
+        self._lib = _lib
         self._inp = _Inputs(mesh, bcs, **kw)
         self.n_cells = self._inp.n_cells
         nbytes = state_bytes(mesh, bcs, **kw)
@@ -219,8 +220,11 @@ class Solver:
         _check(_lib.sdugks_debug_poison(self._h, int(cell), int(i)))
 
     def close(self):
-        if getattr(self, "_h", None):
-            _lib.sdugks_destroy(self._h)
+        # the library is reached through the object: at interpreter exit the
+        # module globals may already be gone when this runs from __del__
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "_h", None) and lib is not None:
+            lib.sdugks_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -232,6 +236,7 @@ class Batch:
     stay usable alone).  With no stream given the library makes its own."""
 
     def __init__(self, members, stream=None):
+        self._lib = _lib
         self.members = list(members)
         arr = (C.c_void_p * len(self.members))(*[m.handle for m in self.members])
         self.stream = stream
@@ -250,8 +255,9 @@ class Batch:
         _check(_lib.sdugks_batch_step(self._b, int(n)))
 
     def close(self):
-        if getattr(self, "_b", None):
-            _lib.sdugks_batch_destroy(self._b)
+        lib = getattr(self, "_lib", None)
+        if getattr(self, "_b", None) and lib is not None:
+            lib.sdugks_batch_destroy(self._b)
             self._b = None
 
     def __del__(self):
