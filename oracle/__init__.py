@@ -169,3 +169,24 @@ class Oracle:
         fbar, fface, phi = np.zeros((n, 9)), np.zeros((n, 9)), np.zeros((n, 9))
         self._lib.orc_face_states(self._h, _p(fbar), _p(fface), _p(phi))
         return fbar, fface, phi
+
+    def boundary_flux(self):
+        """Fluxes through the plain (not periodic) boundary faces on the current
+        state, one row per face in the caller's order of those boundary edges:
+        (mass flux, x-momentum flux, y-momentum flux, face density).  The fluxes
+        are the moments (1, e_x, e_y) of l (e_i . n) f_face (Eq. MesoFlux and
+        Eq. MacroFlux) with n pointing out of the fluid, so the momentum columns
+        are the force the fluid exerts on the boundary; the face density is the
+        zeroth moment of the reconstructed fbar (pressure = density / 3)."""
+        fc = self.faces()
+        fbar, _, phi = self.face_states()
+        sel = np.nonzero(fc["nbr"] < 0)[0]
+        ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
+        ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
+        out = np.zeros((len(sel), 4))
+        for r, f in enumerate(sel):
+            out[r, 0] = sum(phi[f, i] for i in range(9))
+            out[r, 1] = sum(ex[i] * phi[f, i] for i in range(9))
+            out[r, 2] = sum(ey[i] * phi[f, i] for i in range(9))
+            out[r, 3] = sum(fbar[f, i] for i in range(9))
+        return out, fc["bc"][sel]

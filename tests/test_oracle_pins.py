@@ -383,3 +383,70 @@ def test_lagged_and_current_share_the_steady_state(oracle_mod):
         res.append((rho / o.mass(), u, v))
     for a, b in zip(res[0], res[1]):
         assert np.abs(a - b).max() <= 1e-10
+
+
+# ---- boundary fluxes (wall force, surface pressure)
+
+def test_boundary_flux_couette_wall_stress(oracle_mod):
+    """Steady Couette flow: the x-momentum leaving the fluid through each wall
+    is the viscous stress rho nu U/H times the wall width (bottom wall dragged
+    forward, moving top wall held back), the y-momentum is the pressure
+    rho c_s^2 = rho/3 times the width, and no mass crosses a wall."""
+    for ny in (8, 16):
+        mesh, bcs = meshgen.couette(4, ny)
+        o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
+        g = o.geometry()
+        n = o.n_cells
+        f = np.array([oracle_mod.feq(1.0, 0.1 * y, 0.0) for y in g["cy"]])
+        o.set_state(f, np.c_[np.ones(n), 0.1 * g["cy"], np.zeros(n)])
+        o.step(3000)
+        out, tag = o.boundary_flux()
+        width = 4.0 / ny
+        shear = 0.01 * 0.1 / 1.0 * width
+        for t, sgn in ((0, 1.0), (1, -1.0)):
+            s = out[tag == t].sum(0)
+            assert abs(s[1] - sgn * shear) <= 1e-12 * shear
+            assert abs(s[2] + sgn * width / 3.0) <= 1e-13 * width
+            assert abs(s[0]) <= 1e-15
+            assert np.allclose(out[tag == t, 3], 1.0, rtol=0, atol=1e-13)
+
+
+def test_boundary_flux_at_rest_is_pressure_only(oracle_mod):
+    """A fluid at rest pushes on every resting wall face with rho/3 times its
+    scaled normal and nothing else; over a closed wall (the cylinder) the
+    pushes cancel."""
+    mesh, bcs = meshgen.cylinder_ogrid(24, 8, seed=1)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
+    n = o.n_cells
+    o.set_state(np.tile(oracle_mod.feq(1.3, 0.0, 0.0), (n, 1)), np.tile([1.3, 0.0, 0.0], (n, 1)))
+    out, tag = o.boundary_flux()
+    fc = o.faces()
+    sel = fc["nbr"] < 0
+    wall = tag == 0
+    lnx, lny = fc["lnx"][sel][wall], fc["lny"][sel][wall]
+    assert np.abs(out[wall, 1] - 1.3 / 3 * lnx).max() <= 1e-15
+    assert np.abs(out[wall, 2] - 1.3 / 3 * lny).max() <= 1e-15
+    assert np.abs(out[wall, 0]).max() <= 1e-16 and np.abs(out[wall, 3] - 1.3).max() <= 1e-15
+    assert np.abs(out[wall, 1:3].sum(0)).max() <= 1e-15
+
+
+def test_boundary_flux_closes_the_momentum_budget(oracle_mod):
+    """Interior face fluxes cancel between their two cells, so one step
+    changes the total momentum by -dt times the momentum leaving through the
+    boundary faces, evaluated on the state the step starts from."""
+    for mesh, bcs, kw in ((*meshgen.cavity(10), dict(nu=0.01)),
+                          (*meshgen.cylinder_ogrid(24, 8, seed=3), dict(nu=0.004, u0=0.1)),
+                          (*meshgen.inlet_outlet_box(8, 6), dict(nu=0.01, u0=0.05))):
+        o = oracle_mod.Oracle(mesh, bcs, cfl=0.5, **kw)
+        f, W, _ = meshgen.random_state(o.n_cells, seed=21, amp=0.02)
+        o.set_state(f, np.c_[f.sum(1), f @ EX, f @ EY])
+        area = o.geometry()["area"]
+        for _ in range(3):
+            out, _ = o.boundary_flux()
+            _, W0, _ = o.state()
+            o.step(1)
+            _, W1, _ = o.state()
+            dmom = (area[:, None] * (W1[:, 1:] - W0[:, 1:])).sum(0)
+            expect = -o.dt * out[:, 1:3].sum(0)
+            scale = np.abs(area[:, None] * W0[:, 1:]).sum()
+            assert np.abs(dmom - expect).max() <= 1e-14 * scale
