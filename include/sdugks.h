@@ -96,7 +96,9 @@ typedef struct {
                                      library (the fused step orders cells tile by tile instead) */
     int32_t residual_interval;    /* steps between residual checks in serving loops (paper: 1000) */
     int32_t tile_cells;           /* fused one-kernel step over tiles of at most this many cells
-                                     (0 = library default, -1 = two-kernel step without tiles) */
+                                     (0 = library default, -1 = two-kernel step without tiles; meshes with
+                                     polygons of more than four faces or more than 64 boundary-condition
+                                     entries always take the two-kernel step) */
     int32_t block_threads;        /* threads per workgroup of the fused step: 64, 128 or 256 (0 = default) */
 } sdugks_params;
 
@@ -152,6 +154,21 @@ int sdugks_residual(sdugks_t *h, double *eps);
 
 /* mass = sum_j V_j rho_j, deterministic FP64 reduction.  Synchronises. */
 int sdugks_mass(sdugks_t *h, double *mass);
+
+/* Fluxes through the plain (not periodic) boundary faces on the current state:
+ * the face distribution of Eq. f_t_n+1 (with the boundary rule of Section III)
+ * and its flux moments (1, e_x, e_y) of Eqs. MesoFlux / MacroFlux, with the
+ * face normal pointing out of the fluid -- so the two momentum fluxes through a
+ * wall are the force the fluid exerts on it (drag and lift of the circular
+ * cylinder case are these, summed over its wall).  FP64 arithmetic.
+ *   faces   host [n_faces][4] or NULL: per face mass flux, x-momentum flux,
+ *           y-momentum flux and face density rho_f (pressure rho_f / 3), in
+ *           the caller's order of its non-periodic boundary edges;
+ *   sum     host [3] or NULL: the three fluxes summed over the faces whose
+ *           boundary tag is `tag` (all faces when tag < 0), deterministic;
+ *   n_faces host or NULL: number of plain boundary faces.
+ * SDUGKS_EINVAL for a tag beyond the boundary-condition table.  Synchronises. */
+int sdugks_boundary_flux(sdugks_t *h, int32_t tag, double *faces, double *sum, int32_t *n_faces);
 
 /* Any output may be NULL. */
 int sdugks_info(sdugks_t *h, double *dt, double *tau, int64_t *step, int32_t *n_cells);

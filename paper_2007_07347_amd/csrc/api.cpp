@@ -42,6 +42,7 @@ struct Layout {
     size_t off_nbr = 0, off_geo = 0, off_ainv = 0, off_dtv = 0, off_area = 0, off_bft = 0, off_bcs = 0;
     size_t off_part = 0, off_out = 0, total = 0;
     size_t off_thdr = 0, off_lgid = 0, off_ladj = 0, off_lw = 0;
+    size_t off_bq_hdr = 0, off_bq_nb = 0, off_bq_w = 0, off_bq_geo = 0, off_bq_out = 0, off_bq_sum = 0;
 };
 
 // What the three step forms need: the two-kernel step keeps fbar+ and its
@@ -81,6 +82,14 @@ Layout make_layout(const MeshBuild &mb, int precision)
     L.off_bcs = take(std::max<size_t>(1, mb.bcs.size()) * sizeof(DevBC));
     L.off_part = take(4 * kReduceBlocks * sizeof(double));
     L.off_out = take(4 * sizeof(double));
+    // boundary-face table of the flux diagnostic
+    const size_t nbq = std::max<int32_t>(1, mb.n_bfaces);
+    L.off_bq_hdr = take(nbq * sizeof(int4));
+    L.off_bq_nb = take(nbq * mb.D * sizeof(int32_t));
+    L.off_bq_w = take(nbq * mb.D * sizeof(double2));
+    L.off_bq_geo = take(nbq * 2 * sizeof(double2));
+    L.off_bq_out = take(nbq * 4 * sizeof(double));
+    L.off_bq_sum = take(4 * sizeof(double));
     L.total = p;
     return L;
 }
@@ -102,6 +111,7 @@ struct sdugks_s {
     int block = 256;
     DevMesh dm{};
     DevTiles dt{};
+    DevBnd bq{};
     double *host4 = nullptr;     // pinned, 4 doubles
 
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
@@ -364,6 +374,43 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         if (!bcs.empty() && hipMemcpy(h->at<DevBC>(L.off_bcs), bcs.data(), bcs.size() * sizeof(DevBC), hipMemcpyHostToDevice) != hipSuccess)
             return cleanup(fail(SDUGKS_EHIP, "upload of the boundary table failed"));
     }
+    {
+        // boundary-face table: cell, slot and tag of every plain boundary face,
+        // the cell's stencil and weights, the face's l n and r_self
+        const size_t nbf = mb.n_bfaces, D = mb.D;
+        std::vector<int4> hdr(std::max<size_t>(1, nbf), int4{0, 0, 0, 0});
+        std::vector<int32_t> nb(std::max<size_t>(1, nbf) * D, -1);
+        std::vector<double2> w(std::max<size_t>(1, nbf) * D, double2{0.0, 0.0});
+        std::vector<double2> geo(std::max<size_t>(1, nbf) * 2, double2{0.0, 0.0});
+        for (size_t k = 0; k < nc; k++)
+            for (size_t sl = 0; sl < D; sl++) {
+                const int32_t v = mb.nbr[sl * nc + k];
+                if (v >= 0 || v == kEmptySlot) continue;
+                const size_t b = (size_t)(-1 - v), q = sl * nc + k;
+                hdr[b] = int4{(int)k, (int)sl, mb.bf_tag[b], 0};
+                geo[2 * b] = double2{mb.lnx[q], mb.lny[q]};
+                geo[2 * b + 1] = double2{mb.rsx[q], mb.rsy[q]};
+                for (size_t j = 0; j < D; j++) {
+                    const size_t qj = j * nc + k;
+                    const int32_t u = mb.nbr[qj];
+                    nb[b * D + j] = u == kEmptySlot ? -1 : (u >= 0 ? u : -2 - mb.bf_tag[-1 - u]);
+                    w[b * D + j] = double2{mb.wx[qj], mb.wy[qj]};
+                }
+            }
+        auto upb = [&](size_t off, const void *src, size_t bytes) {
+            return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+        };
+        if (!upb(L.off_bq_hdr, hdr.data(), hdr.size() * sizeof(int4)) || !upb(L.off_bq_nb, nb.data(), nb.size() * sizeof(int32_t)) ||
+            !upb(L.off_bq_w, w.data(), w.size() * sizeof(double2)) || !upb(L.off_bq_geo, geo.data(), geo.size() * sizeof(double2)))
+            return cleanup(fail(SDUGKS_EHIP, "upload of the boundary-face table failed"));
+        h->bq.n = (int32_t)nbf;
+        h->bq.hdr = h->at<int4>(L.off_bq_hdr);
+        h->bq.nb = h->at<int32_t>(L.off_bq_nb);
+        h->bq.w = h->at<double2>(L.off_bq_w);
+        h->bq.geo = h->at<double2>(L.off_bq_geo);
+        h->bq.out = h->at<double>(L.off_bq_out);
+        h->bq.sum = h->at<double>(L.off_bq_sum);
+    }
     if (tiled) {
         auto up = [&](size_t off, const void *src, size_t bytes) {
             return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
@@ -601,6 +648,21 @@ int sdugks_mass(sdugks_t *h, double *mass)
     if (rc) return rc;
     *mass = r[2];
     if (r[3] != 0.0) return fail(SDUGKS_EDIVERGED, "non-finite density or velocity");
+    return SDUGKS_OK;
+}
+
+int sdugks_boundary_flux(sdugks_t *h, int32_t tag, double *faces, double *sum, int32_t *n_faces)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    if (tag >= (int32_t)h->mb.bcs.size()) return fail(SDUGKS_EINVAL, "tag beyond the boundary-condition table");
+    HIPCHK(hipSetDevice(h->device));
+    HIPCHK(launch_boundary_flux(h->dm, h->state(), h->bq, h->dev32(), tag, h->stream));
+    if (faces && h->bq.n > 0)
+        HIPCHK(hipMemcpyAsync(faces, h->bq.out, (size_t)h->bq.n * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(h->host4, h->bq.sum, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (sum) std::memcpy(sum, h->host4, 3 * sizeof(double));
+    if (n_faces) *n_faces = h->bq.n;
     return SDUGKS_OK;
 }
 

@@ -72,6 +72,22 @@ struct BatchTable {
     const int32_t *count;
 };
 
+// Plain boundary faces for the face-flux diagnostic, in the caller's order of
+// its non-periodic boundary edges: the adjacent cell, the face's slot and tag,
+// the cell's least-squares stencil (neighbour >= 0, -2 - tag for a boundary
+// point, -1 empty) with its weights, and the face's scaled normal l n and
+// midpoint offset r_self.  out [n][4]: mass flux, x- and y-momentum flux
+// leaving the fluid, face density; sum [3]: the fluxes summed over one tag.
+struct DevBnd {
+    int32_t n;
+    const int4 *hdr;                    // [n]: cell, slot, tag, 0
+    const int32_t *nb;                  // [n][D]
+    const double2 *w;                   // [n][D]
+    const double2 *geo;                 // [n][2]: l n, r_self
+    double *out;
+    double *sum;
+};
+
 struct DevScratch {
     double *fbp;                        // [9][np] fbar+ at the cell centres
     double *sg;                         // [18][np] its least-squares gradient (x rows 0..8, y rows 9..17)
@@ -92,6 +108,9 @@ hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity
 // snap = [2][np] (U, V); update_snap re-snapshots.
 hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int update_snap, double *partials,
                          double *out4, hipStream_t st);
+// Boundary face fluxes on the state s (FP64 f, or the deviation form when
+// dev32), then their sums over the faces of `tag` (all when tag < 0).
+hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBnd &q, int dev32, int tag, hipStream_t st);
 // *p = NaN, p pointing at a double (bytes 8) or a float (bytes 4): failure injection.
 hipError_t launch_poke_nan(void *p, int bytes, hipStream_t st);
 

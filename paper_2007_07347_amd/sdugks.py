@@ -56,6 +56,7 @@ _sig = {
     "sdugks_residual": [_P, _P],
     "sdugks_mass": [_P, _P],
     "sdugks_info": [_P, _P, _P, _P, _P],
+    "sdugks_boundary_flux": [_P, C.c_int32, _P, _P, _P],
     "sdugks_step_profiled": [_P, C.c_int64, _P, _P, C.c_int32, _P],
     "sdugks_destroy": [_P],
     "sdugks_last_error": [],
@@ -218,6 +219,20 @@ class Solver:
 
     def poison(self, cell, i):
         _check(_lib.sdugks_debug_poison(self._h, int(cell), int(i)))
+
+    def boundary_flux(self, tag=-1):
+        """Fluxes through the plain boundary faces on the current state:
+        (faces [n][4] = mass flux, x-momentum flux, y-momentum flux, face
+        density, in the order of the non-periodic boundary edges; sums [3] of
+        the three fluxes over the faces of `tag`, all faces when tag < 0).
+        The momentum columns are the force the fluid exerts on the boundary."""
+        n = C.c_int32()
+        _check(_lib.sdugks_boundary_flux(self._h, int(tag), None, None, C.byref(n)))
+        faces = np.zeros((n.value, 4))
+        sums = np.zeros(3)
+        _check(_lib.sdugks_boundary_flux(self._h, int(tag), faces.ctypes.data if n.value else None,
+                                         sums.ctypes.data, None))
+        return faces, sums
 
     def close(self):
         # the library is reached through the object: at interpreter exit the
