@@ -11,8 +11,9 @@ the batched form on 64 uneven cavities (edge log-uniform in [32, 512] cells,
 Re uniform in [100, 5000], FP32 deviation storage) against stepping the same
 instances one after another; the continuous-batching serving loop on a finite
 seeded request trace with p50/p99 time-to-steady, against the per-case FP64
-loop; the HBM roofline of the step kernel; and the CPU oracle timed on a
-bounded sample of the headline workload.
+loop; steady drag, lift, stagnation pressure and recirculation length of the
+circular cylinder at Re = 10, 20, 40; the HBM roofline of the step kernel; and
+the CPU oracle timed on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
     python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
@@ -187,6 +188,35 @@ def serving(meshgen, seed=7, n_requests=24, step_cap=150_000):
             "per_case_fp64_loop": {k: (r3(v) if isinstance(v, float) else v) for k, v in st_s.items()}}
 
 
+def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
+    """Steady flow around a circular cylinder (O-grid, far field at 20
+    diameters, 50,000 triangles, FP64) at Re = 10, 20, 40, each marched from
+    the free stream until the velocity residual of successive checks (every
+    2000 steps) is below tol: drag and lift coefficients from the wall
+    momentum flux, stagnation pressure coefficient and recirculation length.
+    The paper's table values (its own 75d x 50d domain and meshes) are given
+    for context."""
+    import math
+    import numpy as np
+    from paper_2007_07347_amd import cylinder, sdugks
+    paper = {10: (3.015, 0.493), 20: (2.115, 1.842), 40: (1.557, 4.490)}
+    mesh, bcs = meshgen.cylinder_ogrid(n_theta, n_r, seed=0)
+    rows = []
+    for re in (10, 20, 40):
+        t0 = time.perf_counter()
+        s, r = cylinder.run_steady(sdugks, mesh, bcs, re, tol=tol, interval=2000, cfl=0.5)
+        L = cylinder.recirculation_length(s, mesh, bcs, nu=0.1 / re, cfl=0.5, u0=0.1)
+        th, cp = cylinder.pressure_coefficient(s, mesh, bcs)
+        rows.append({"Re": re, "steps": r["steps"], "residual": float(f"{r['residual']:.3g}"),
+                     "Cd": round(float(r["Cd"]), 4), "Cl": float(f"{r['Cl']:.2g}"), "L_over_R": round(2.0 * L, 3),
+                     "Cp_front": round(float(cp[np.argmin(np.abs(th - math.pi))]), 3),
+                     "dt_over_tau": round(s.dt / s.tau, 4), "wall_s": round(time.perf_counter() - t0, 1),
+                     "paper_Cd": paper[re][0], "paper_L_over_R": paper[re][1]})
+        s.close()
+    return {"workload": f"circular cylinder, O-grid {n_theta}x{n_r} split into {2 * n_theta * n_r} triangles, "
+                        f"r 0.5..20, u_inf 0.1, FP64, to residual {tol:g}", "cases": rows}
+
+
 def cpu_baseline(mesh, bcs, kw, target_s):
     import oracle
     kw = {k: v for k, v in kw.items() if k in ("nu", "cfl")}
@@ -254,6 +284,7 @@ def main():
         s32.close()
         out["batch"] = batch_form(sdugks, autotune, meshgen)
         out["serving"] = serving(meshgen)
+        out["cylinder"] = cylinder_form(meshgen)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, bcs, kw, a.cpu_seconds)
     print(json.dumps(out), flush=True)
