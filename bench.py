@@ -12,7 +12,8 @@ Re uniform in [100, 5000], FP32 deviation storage) against stepping the same
 instances one after another; the continuous-batching serving loop on a finite
 seeded request trace with p50/p99 time-to-steady, against the per-case FP64
 loop; steady drag, lift, stagnation pressure and recirculation length of the
-circular cylinder at Re = 10, 20, 40; the HBM roofline of the step kernel; and
+circular cylinder at Re = 10, 20, 40 and its Strouhal number and mean drag at
+Re = 60, 80, 100; the HBM roofline of the step kernel; and
 the CPU oracle timed on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
@@ -213,8 +214,20 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
                      "dt_over_tau": round(s.dt / s.tau, 4), "wall_s": round(time.perf_counter() - t0, 1),
                      "paper_Cd": paper[re][0], "paper_L_over_R": paper[re][1]})
         s.close()
+    unsteady = []
+    paper_u = {60: (1.4228, 0.1377), 80: (1.375, 0.1523), 100: (1.349, 0.1653)}
+    for re in (60, 80, 100):
+        t0 = time.perf_counter()
+        s, r = cylinder.run_shedding(sdugks, mesh, bcs, re, t_transient=1500.0, t_sample=500.0, cfl=0.5, kick=0.2)
+        s.close()
+        unsteady.append({"Re": re, "St": round(r["St"], 4), "Cd_mean": round(r["Cd_mean"], 4),
+                         "Cl_amp": round(r["Cl_amp"], 4), "steps": r["steps"], "wall_s": round(time.perf_counter() - t0, 1),
+                         "St_fit": round(-3.3265 / re + 0.1816 + 1.6e-4 * re, 4),
+                         "paper_Cd": paper_u[re][0], "paper_St": paper_u[re][1]})
     return {"workload": f"circular cylinder, O-grid {n_theta}x{n_r} split into {2 * n_theta * n_r} triangles, "
-                        f"r 0.5..20, u_inf 0.1, FP64, to residual {tol:g}", "cases": rows}
+                        f"r 0.5..20, u_inf 0.1, FP64; steady cases to residual {tol:g}, unsteady cases "
+                        f"1500 time units of transient (transverse kick 0.2 u_inf in the near wake) then 500 sampled",
+            "steady": rows, "unsteady": unsteady}
 
 
 def cpu_baseline(mesh, bcs, kw, target_s):

@@ -1,0 +1,30 @@
+"""Host post-processing of the cylinder case on synthetic data: the shedding
+frequency estimator and the wake-axis interpolation."""
+import numpy as np
+
+from paper_2007_07347_amd import cylinder
+
+
+def test_dominant_frequency_recovers_a_sinusoid():
+    rng = np.random.default_rng(0)
+    for f0 in (0.0137, 0.01523, 0.0166):
+        t = 600.0 + 0.37 * np.arange(1400)
+        x = 0.3 * np.sin(2 * np.pi * f0 * t + 0.4) + 0.01 * np.sin(2 * np.pi * 2 * f0 * t) + 1e-3 * rng.standard_normal(len(t))
+        assert abs(cylinder.dominant_frequency(t, x) - f0) <= 2e-3 * f0
+
+
+def test_axis_velocity_is_exact_for_linear_fields():
+    rng = np.random.default_rng(1)
+    cx, cy = rng.uniform(0.5, 10, 4000), rng.uniform(-1, 1, 4000)
+    u = 0.1 * (cx - 3.0) + 0.02 * cy
+    xs = np.linspace(0.6, 9.0, 50)
+    assert np.abs(cylinder.axis_velocity(cx, cy, u, xs) - 0.1 * (xs - 3.0)).max() <= 1e-12
+
+
+def test_equilibrium_moments():
+    rho, u, v = np.array([1.0, 1.2]), np.array([0.1, -0.05]), np.array([0.0, 0.03])
+    f = cylinder.equilibrium(rho, u, v)
+    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1.0])
+    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1.0])
+    assert np.allclose(f.sum(1), rho, atol=1e-15)
+    assert np.allclose(f @ ex, rho * u, atol=1e-15) and np.allclose(f @ ey, rho * v, atol=1e-15)

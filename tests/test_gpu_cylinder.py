@@ -61,3 +61,27 @@ def test_recirculation_and_pressure(runs):
         assert r["cp_front"] > 1.0, (re, r["cp_front"])
     assert runs[10]["LR"] < runs[20]["LR"] < runs[40]["LR"]
     assert runs[10]["cp_front"] > runs[20]["cp_front"] > runs[40]["cp_front"]
+
+
+def test_vortex_shedding_re100():
+    """Re = 100: periodic shedding (seeded by a transverse kick in the near
+    wake), saturated lift oscillation.  Bands: Strouhal number within 3 % of
+    the experimental fit the paper cites (St = -3.3265/Re + 0.1816 + 1.6e-4 Re
+    = 0.1643) and of the paper's 0.1653, mean drag within 5 % of the paper's
+    1.349, lift amplitude of a developed street (0.25 .. 0.45) that no longer
+    grows, drag oscillating at twice the shedding frequency."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_07347_amd import cylinder, sdugks
+    mesh, bcs = meshgen.cylinder_ogrid(128, 64, seed=0)
+    s, r = cylinder.run_shedding(sdugks, mesh, bcs, 100, t_transient=1500.0, t_sample=500.0, cfl=0.5, kick=0.2)
+    s.close()
+    print({k: v for k, v in r.items() if k not in ("t", "Cd", "Cl")}, flush=True)
+    fit = -3.3265 / 100 + 0.1816 + 1.6e-4 * 100
+    assert abs(r["St"] - fit) <= 0.03 * fit and abs(r["St"] - 0.1653) <= 0.03 * 0.1653
+    assert abs(r["Cd_mean"] - 1.349) <= 0.05 * 1.349
+    assert 0.25 <= r["Cl_amp"] <= 0.45
+    q = len(r["Cl"]) // 4
+    assert abs(np.ptp(r["Cl"][:q]) - np.ptp(r["Cl"][-q:])) <= 0.02 * np.ptp(r["Cl"])
+    f_cd = cylinder.dominant_frequency(r["t"], r["Cd"])
+    assert abs(f_cd - 2.0 * r["St"] * 0.1) <= 0.05 * 2.0 * r["St"] * 0.1
