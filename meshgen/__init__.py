@@ -168,15 +168,18 @@ def jittered_periodic_triangles(n, seed=0, jitter=0.2, length=1.0):
     return mesh, bcs
 
 
-def cylinder_ogrid(n_theta=400, n_r=250, r_wall=0.5, r_far=20.0, jitter=0.1, seed=0, U=0.1):
+def cylinder_ogrid(n_theta=400, n_r=250, r_wall=0.5, r_far=20.0, jitter=0.1, seed=0, U=0.1, quad_layers=0):
     """Annular O-grid around a circular cylinder of diameter 2*r_wall, split into
     triangles (paper, flow around a circular cylinder, on a synthetic mesh).
 
     Radii grow geometrically, r_k = r_wall (r_far/r_wall)^(k/n_r); interior
     nodes are jittered radially by U(-jitter, jitter) of the smaller adjacent
     radial spacing and tangentially by U(-jitter, jitter) of r_k * dtheta; each
-    quad is split along a seeded diagonal.  Tag 0: the cylinder wall (at rest);
-    tag 1: the far-field circle with the free stream (1, U, 0).
+    quad is split along a seeded diagonal, except those of the first
+    quad_layers rings next to the wall (a hybrid mesh: quads in the boundary
+    layer, triangles outside, like the paper's cylinder meshes).  Tag 0: the
+    cylinder wall (at rest); tag 1: the far-field circle with the free stream
+    (1, U, 0).
     """
     rng = np.random.default_rng(seed)
     k = np.arange(n_r + 1, dtype=np.float64)
@@ -198,18 +201,43 @@ def cylinder_ogrid(n_theta=400, n_r=250, r_wall=0.5, r_far=20.0, jitter=0.1, see
     K, M = np.meshgrid(np.arange(n_r), np.arange(n_theta), indexing="ij")
     K, M = K.ravel(), M.ravel()
     quads = np.stack([nid(K, M), nid(K + 1, M), nid(K + 1, M + 1), nid(K, M + 1)], 1).astype(np.int32)
-    tris = _split_quads(quads, rng.integers(0, 2, size=len(quads)))
+    coin = rng.integers(0, 2, size=len(quads))
     m = np.arange(n_theta)
     bedges = np.concatenate([np.stack([nid(0, m + 1), nid(0, m)], 1), np.stack([nid(n_r, m), nid(n_r, m + 1)], 1)])
     tags = np.concatenate([np.zeros(n_theta), np.ones(n_theta)])
-    mesh = {
-        "node_xy": np.ascontiguousarray(node_xy),
-        "cell_ptr": np.arange(0, 3 * len(tris) + 1, 3, dtype=np.int32),
-        "cell_nodes": np.ascontiguousarray(tris.ravel()),
-        "bedge_nodes": np.ascontiguousarray(bedges.astype(np.int32)),
-        "bedge_tag": np.ascontiguousarray(tags.astype(np.int32)),
-    }
-    return mesh, [bc(WALL, u=0.0), bc(INLET, rho=1.0, u=U, v=0.0)]
+    bcs = [bc(WALL, u=0.0), bc(INLET, rho=1.0, u=U, v=0.0)]
+    if quad_layers <= 0:
+        tris = _split_quads(quads, coin)
+        mesh = {
+            "node_xy": np.ascontiguousarray(node_xy),
+            "cell_ptr": np.arange(0, 3 * len(tris) + 1, 3, dtype=np.int32),
+            "cell_nodes": np.ascontiguousarray(tris.ravel()),
+            "bedge_nodes": np.ascontiguousarray(bedges.astype(np.int32)),
+            "bedge_tag": np.ascontiguousarray(tags.astype(np.int32)),
+        }
+        return mesh, bcs
+    keep = K < quad_layers
+    tris = _split_quads(quads[~keep], coin[~keep])
+    cells = [list(q) for q in quads[keep]] + [list(t) for t in tris]
+    return _pack(node_xy, cells, bedges, tags), bcs
+
+
+def split_some(mesh, frac, seed=0):
+    """The same mesh with a seeded fraction of its quads each split into two
+    triangles along a seeded diagonal (a hybrid quad/triangle mesh); split
+    quads are replaced in place by their two triangles, boundary edges are
+    unchanged."""
+    rng = np.random.default_rng(seed)
+    ptr, nodes = mesh["cell_ptr"], mesh["cell_nodes"]
+    cells = []
+    for c in range(len(ptr) - 1):
+        poly = nodes[ptr[c]:ptr[c + 1]]
+        if len(poly) == 4 and rng.uniform() < frac:
+            t = _split_quads(np.asarray([poly]), rng.integers(0, 2, size=1))
+            cells += [list(t[0]), list(t[1])]
+        else:
+            cells.append(list(poly))
+    return _pack(mesh["node_xy"], cells, mesh["bedge_nodes"], mesh["bedge_tag"])
 
 
 def relabel(mesh, seed):

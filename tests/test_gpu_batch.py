@@ -27,6 +27,7 @@ def members(sd):
         (meshgen.cylinder_ogrid(48, 16, seed=3), dict(nu=2.5e-3, u0=0.1)),
         (meshgen.jittered_periodic_triangles(12, seed=4), dict(nu=4e-3, precision=sd.FP32DEV)),
         (meshgen.couette(4, 32), dict(nu=1e-2, macro=sd.MACRO_LAGGED, cfl=0.3)),
+        (meshgen.cylinder_ogrid(40, 12, seed=7, quad_layers=4), dict(nu=2.5e-3, u0=0.1, precision=sd.FP32DEV)),
     ]
     return specs
 

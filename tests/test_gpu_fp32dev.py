@@ -35,6 +35,7 @@ CASES = {
     "periodic_tri_9": (lambda: meshgen.jittered_periodic_triangles(9, seed=6), dict(nu=0.004, cfl=0.5)),
     "inlet_outlet_13x9": (lambda: meshgen.inlet_outlet_box(13, 9), dict(nu=0.005, cfl=0.5)),
     "couette_5x16": (lambda: meshgen.couette(5, 16), dict(nu=0.01, cfl=0.5)),
+    "hybrid_ogrid_40x12": (lambda: meshgen.cylinder_ogrid(40, 12, seed=7, quad_layers=4), dict(nu=0.0025, cfl=0.5, u0=0.1)),
 }
 
 

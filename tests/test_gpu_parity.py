@@ -85,6 +85,10 @@ def _small_cases():
         "periodic_tri_9": (lambda: meshgen.jittered_periodic_triangles(9, seed=6), dict(nu=0.004, cfl=0.5)),
         "hexagons_7x5": (lambda: meshgen.hexagon_strip(7, 5), dict(nu=0.01, cfl=0.5)),
         "inlet_outlet_13x9": (lambda: meshgen.inlet_outlet_box(13, 9), dict(nu=0.005, cfl=0.5)),
+        "hybrid_ogrid_40x12": (lambda: meshgen.cylinder_ogrid(40, 12, seed=7, quad_layers=4),
+                               dict(nu=0.0025, cfl=0.5, u0=0.1)),
+        "hybrid_cavity_17": (lambda: (meshgen.split_some(meshgen.cavity(17)[0], 0.3, seed=4), meshgen.cavity(17)[1]),
+                             dict(nu=0.001, cfl=0.5)),
         "relabeled_cavity_11": (lambda: (meshgen.relabel(meshgen.cavity(11)[0], seed=2)[0], meshgen.cavity(11)[1]),
                                 dict(nu=0.002, cfl=0.5)),
     }

@@ -81,7 +81,7 @@ def test_geometry_closes_and_tiles(oracle_mod):
 
 
 # ------------------------------------------------------------ least squares
-@pytest.mark.parametrize("which", ["cartesian", "triangles", "ogrid"])
+@pytest.mark.parametrize("which", ["cartesian", "triangles", "ogrid", "hybrid"])
 def test_lsq_exact_on_linear_fields(oracle_mod, which):
     """The LLSR normal equations return the exact gradient of a linear field
     alpha + beta . x on every cell (any non-degenerate stencil), with the
@@ -90,6 +90,8 @@ def test_lsq_exact_on_linear_fields(oracle_mod, which):
         mesh, bcs = meshgen.cavity(12)
     elif which == "triangles":
         mesh, bcs = meshgen.jittered_periodic_triangles(6, seed=2)
+    elif which == "hybrid":
+        mesh, bcs = meshgen.cylinder_ogrid(24, 10, seed=5, quad_layers=4)
     else:
         mesh, bcs = meshgen.cylinder_ogrid(24, 10, seed=5)
     o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
@@ -212,10 +214,11 @@ def _tiny_cases():
     m4, b4 = meshgen.structured(np.linspace(0, 1, 4), np.linspace(0, 1, 5), 0, 1, 2, 3), \
         [meshgen.bc(meshgen.WALL), meshgen.bc(meshgen.OUTLET), meshgen.bc(meshgen.WALL, u=0.1),
          meshgen.bc(meshgen.INLET, u=0.05, v=0.01)]
-    return [(m1, b1), (m2, b2), (m3, b3), (m4, b4)]
+    m5, b5 = meshgen.split_some(meshgen.cavity(4)[0], 0.5, seed=2), meshgen.cavity(4)[1]   # quads and triangles
+    return [(m1, b1), (m2, b2), (m3, b3), (m4, b4), (m5, b5)]
 
 
-@pytest.mark.parametrize("case", range(4))
+@pytest.mark.parametrize("case", range(5))
 def test_brute_force_equals_assembled(oracle_mod, case):
     """Per-face evaluation with a fresh Cramer solve and face-order scatter
     agrees with the assembled per-cell gather over 50 steps."""
@@ -231,7 +234,7 @@ def test_brute_force_equals_assembled(oracle_mod, case):
         assert np.abs(a - b).max() <= 1e-14 * max(1.0, np.abs(b).max())
 
 
-@pytest.mark.parametrize("which", ["cavity", "ogrid", "couette"])
+@pytest.mark.parametrize("which", ["cavity", "ogrid", "couette", "hybrid"])
 def test_relabel_and_orientation_invariance(oracle_mod, which):
     """Renumbering cells, rotating polygon node lists and flipping boundary
     edges (which changes face owners and normal orientations, including the
@@ -240,6 +243,8 @@ def test_relabel_and_orientation_invariance(oracle_mod, which):
         mesh, bcs = meshgen.cavity(8)
     elif which == "couette":
         mesh, bcs = meshgen.couette(4, 8)
+    elif which == "hybrid":
+        mesh, bcs = meshgen.cylinder_ogrid(16, 6, seed=1, quad_layers=2)
     else:
         mesh, bcs = meshgen.cylinder_ogrid(16, 6, seed=1)
     mesh2, perm = meshgen.relabel(mesh, seed=5)
