@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-WALL, INLET, OUTLET, PERIODIC = 1, 2, 3, 4
+WALL, INLET, OUTLET, PERIODIC, SYMMETRY = 1, 2, 3, 4, 5
 
 
 def bc(type_, rho=1.0, u=0.0, v=0.0, partner=-1, shift=(0.0, 0.0)):
@@ -270,6 +270,23 @@ def mirror_x(mesh, x_axis=0.5):
     ptr, nodes = mesh["cell_ptr"], mesh["cell_nodes"]
     cells = [nodes[ptr[c]:ptr[c + 1]][::-1] for c in range(len(ptr) - 1)]
     return _pack(xy, cells, mesh["bedge_nodes"], mesh["bedge_tag"])
+
+
+def rotate(mesh, bcs, angle):
+    """The mesh rotated by `angle` (radians) about the origin, with the
+    boundary table's velocities and periodic shifts rotated alike."""
+    c, s = math.cos(angle), math.sin(angle)
+    xy = mesh["node_xy"] @ np.array([[c, s], [-s, c]])
+    out = dict(mesh)
+    out["node_xy"] = np.ascontiguousarray(xy)
+    nb = []
+    for b in bcs:
+        b = dict(b)
+        b["u"], b["v"] = c * b["u"] - s * b["v"], s * b["u"] + c * b["v"]
+        sx, sy = b["shift"]
+        b["shift"] = (c * sx - s * sy, s * sx + c * sy)
+        nb.append(b)
+    return out, nb
 
 
 def random_state(n_cells, seed, amp=0.05, rho0=1.0):

@@ -24,7 +24,9 @@
  * of fbar comes from the boundary state f_b = feq(rho_b, u_b) + (f_in - feq_in)
  * with (rho_b, u_b) = (rho_in, u_wall) on walls, (rho_inf, u_inf) on inlets,
  * (rho_in, u_in) on outlets; for e_i . N >= 0 it comes from the interior
- * reconstruction.  Periodic sides are glued into interior faces with a
+ * reconstruction.  Symmetry faces (ghost cells mirrored about the boundary):
+ * (rho_b, u_b) = (rho_in, u_in - (u_in . N) N), the mean of the inner cell and
+ * its mirror image, in the same construction.  Periodic sides are glued into interior faces with a
  * translation (the ghost cells of the periodic condition carry the partner
  * cell's state, so gluing is the same thing).
  *
@@ -240,7 +242,8 @@ orc_case *orc_create(int n_nodes, const double *xy, int nc, const int *cptr, con
     for (int e = 0; e < nbe; e++) {
         int t = btag[e];
         if (bct[t] == ORC_PERIODIC) continue;
-        if (bct[t] != ORC_WALL && bct[t] != ORC_INLET && bct[t] != ORC_OUTLET) FAIL("bc %d: unknown type %d", t, bct[t]);
+        if (bct[t] != ORC_WALL && bct[t] != ORC_INLET && bct[t] != ORC_OUTLET && bct[t] != ORC_SYMMETRY)
+            FAIL("bc %d: unknown type %d", t, bct[t]);
         int f = nf++;
         double xa = xy[2 * bha[e]], ya = xy[2 * bha[e] + 1], xb = xy[2 * bhb[e]], yb = xy[2 * bhb[e] + 1];
         o->fo[f] = bcell[e]; o->fn[f] = -1; o->fbc[f] = t;
@@ -495,6 +498,13 @@ static void prepare(orc_case *o, int cramer)
         double rb, ub, vb;
         if (o->bct[t] == ORC_WALL) { rb = rho_in; ub = o->bcv[5 * t + 1]; vb = o->bcv[5 * t + 2]; }
         else if (o->bct[t] == ORC_INLET) { rb = o->bcv[5 * t]; ub = o->bcv[5 * t + 1]; vb = o->bcv[5 * t + 2]; }
+        else if (o->bct[t] == ORC_SYMMETRY) {
+            /* the mean of the inner cell and its mirror image about the face:
+             * same density, normal velocity removed, tangential velocity kept */
+            double l = sqrt(o->lnx[f] * o->lnx[f] + o->lny[f] * o->lny[f]);
+            double nx = o->lnx[f] / l, ny = o->lny[f] / l, un = u_in * nx + v_in * ny;
+            rb = rho_in; ub = u_in - un * nx; vb = v_in - un * ny;
+        }
         else { rb = rho_in; ub = u_in; vb = v_in; }
         double feb[9], fein[9];
         orc_feq(rb, ub, vb, feb);

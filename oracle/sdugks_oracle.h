@@ -25,7 +25,7 @@ extern "C" {
 
 typedef struct orc_case orc_case;
 
-enum { ORC_WALL = 1, ORC_INLET = 2, ORC_OUTLET = 3, ORC_PERIODIC = 4 };
+enum { ORC_WALL = 1, ORC_INLET = 2, ORC_OUTLET = 3, ORC_PERIODIC = 4, ORC_SYMMETRY = 5 };
 enum { ORC_LAGGED = 0, ORC_CURRENT = 1 };     /* time level of the macroscopic flux */
 enum { ORC_ASSEMBLED = 0, ORC_BRUTE = 1 };    /* assembly mode */
 

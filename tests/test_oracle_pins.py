@@ -455,3 +455,56 @@ def test_boundary_flux_closes_the_momentum_budget(oracle_mod):
             expect = -o.dt * out[:, 1:3].sum(0)
             scale = np.abs(area[:, None] * W0[:, 1:]).sum()
             assert np.abs(dmom - expect).max() <= 1e-14 * scale
+
+
+# ---- symmetry boundary
+
+def _couette_free_slip(ny=16):
+    """Couette cell with the bottom wall replaced by a symmetry line."""
+    mesh, bcs = meshgen.couette(4, ny)
+    bcs = [dict(b) for b in bcs]
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)
+    return mesh, bcs
+
+
+def test_symmetry_uniform_parallel_flow_is_fixed_point(oracle_mod):
+    """A uniform equilibrium flow along a (slanted) symmetry line is steady:
+    the boundary state is the inner state itself."""
+    mesh, bcs = _couette_free_slip(8)
+    ang = 0.37
+    bcs[1] = meshgen.bc(meshgen.WALL, u=0.08)          # top wall moving with the flow
+    mesh, bcs = meshgen.rotate(mesh, bcs, ang)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
+    n = o.n_cells
+    u, v = 0.08 * math.cos(ang), 0.08 * math.sin(ang)
+    f0 = np.tile(oracle_mod.feq(1.1, u, v), (n, 1))
+    o.set_state(f0, np.tile([1.1, 1.1 * u, 1.1 * v], (n, 1)))
+    o.step(200)
+    f, W, _ = o.state()
+    assert np.abs(f - f0).max() <= 1e-14
+
+
+def test_symmetry_couette_free_slip_moves_with_the_wall(oracle_mod):
+    """A moving wall over a free-slip (symmetry) plane drags the whole layer
+    to its own velocity: the steady state is u = U everywhere, with no shear
+    left on the wall (the diffusive transient decays as exp(-nu (pi/2H)^2 t))."""
+    mesh, bcs = _couette_free_slip(16)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.05, cfl=0.5)
+    o.step(30000)
+    rho, u, v = o.macros()
+    assert np.abs(u - 0.1).max() <= 1e-10 and np.abs(v).max() <= 1e-12
+    out, tag = o.boundary_flux()
+    assert np.abs(out[tag == 1, 1]).sum() <= 1e-12
+
+
+def test_symmetry_brute_force_equals_assembled(oracle_mod):
+    mesh, bcs = meshgen.rotate(*_couette_free_slip(6), 0.9)
+    res = []
+    for assembly in (0, 1):
+        o = oracle_mod.Oracle(mesh, bcs, nu=0.02, cfl=0.5, assembly=assembly)
+        f, W, G = meshgen.random_state(o.n_cells, seed=41)
+        o.set_state(f, W, G)
+        o.step(50)
+        res.append(o.state())
+    for a, b in zip(res[0], res[1]):
+        assert np.abs(a - b).max() <= 1e-14 * max(1.0, np.abs(b).max())
