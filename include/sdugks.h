@@ -49,11 +49,15 @@ enum {
 
 /* Boundary-condition types, Section III.  WALL: rho from the adjacent cell,
  * u = wall velocity.  INLET: (rho_inf, u_inf).  OUTLET: rho and u of the
- * adjacent cell.  All three build the boundary distribution by
- * non-equilibrium extrapolation, f_b = feq(rho_b, u_b) + (f_in - feq_in), and
- * use it for the velocities with e_i . N < 0 (N outward).  PERIODIC: the tag's
- * edges are glued to the partner tag's edges shifted by (shift_x, shift_y). */
-enum { SDUGKS_BC_WALL = 1, SDUGKS_BC_INLET = 2, SDUGKS_BC_OUTLET = 3, SDUGKS_BC_PERIODIC = 4 };
+ * adjacent cell.  SYMMETRY: rho of the adjacent cell and its velocity without
+ * the normal component, u_in - (u_in . N) N (the mean of the cell and its
+ * mirror image about the boundary); the tag's edges must lie on one straight
+ * line (u, v of the entry are ignored).  These four build the boundary
+ * distribution by non-equilibrium extrapolation,
+ * f_b = feq(rho_b, u_b) + (f_in - feq_in), and use it for the velocities with
+ * e_i . N < 0 (N outward).  PERIODIC: the tag's edges are glued to the partner
+ * tag's edges shifted by (shift_x, shift_y). */
+enum { SDUGKS_BC_WALL = 1, SDUGKS_BC_INLET = 2, SDUGKS_BC_OUTLET = 3, SDUGKS_BC_PERIODIC = 4, SDUGKS_BC_SYMMETRY = 5 };
 
 /* Storage precision of f: FP64, or FP32 holding the deviation f - w_i rho0
  * (density, momentum, mass and residual stay FP64). */

@@ -35,6 +35,10 @@ __device__ void bstate(const DevBC &bc, double r, double ux, double uy, double &
 {
     if (bc.type == 2) { rb = bc.rho; ub = bc.u; vb = bc.v; }          // inlet / far field
     else if (bc.type == 3) { rb = r; ub = ux; vb = uy; }              // outlet
+    else if (bc.type == 5) {                                          // symmetry: (u, v) = unit normal
+        const double un = ux * bc.u + uy * bc.v;
+        rb = r; ub = ux - un * bc.u; vb = uy - un * bc.v;
+    }
     else { rb = r; ub = bc.u; vb = bc.v; }                            // wall
 }
 

@@ -33,6 +33,10 @@ __device__ __forceinline__ void boundary_state(const DevBC &bc, double rho, doub
 {
     if (bc.type == 2) { rb = bc.rho; ub = bc.u; vb = bc.v; }          // inlet / far field
     else if (bc.type == 3) { rb = rho; ub = ux; vb = uy; }            // outlet
+    else if (bc.type == 5) {                                          // symmetry: (u, v) = unit normal
+        const double un = ux * bc.u + uy * bc.v;
+        rb = rho; ub = ux - un * bc.u; vb = uy - un * bc.v;
+    }
     else { rb = rho; ub = bc.u; vb = bc.v; }                          // wall (moving or at rest)
 }
 

@@ -281,7 +281,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
         if (kv.second >= 0 && !bseen.count(kv.first)) BAD("cell %d has an untagged free edge", he[kv.second].cell);
     for (int32_t t = 0; t < n_bc; t++) {
         int32_t ty = bc[t].type;
-        if (ty < SDUGKS_BC_WALL || ty > SDUGKS_BC_PERIODIC) BAD("bc %d: unknown type %d", t, ty);
+        if (ty < SDUGKS_BC_WALL || ty > SDUGKS_BC_SYMMETRY) BAD("bc %d: unknown type %d", t, ty);
         if (ty == SDUGKS_BC_INLET && !(bc[t].rho > 0)) BAD("bc %d: inlet density must be positive", t);
         if (ty == SDUGKS_BC_PERIODIC) {
             int32_t p = bc[t].partner;
@@ -289,6 +289,40 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
             double tol = 1e-12 * (1.0 + std::fabs(bc[t].shift_x) + std::fabs(bc[t].shift_y));
             if (std::fabs(bc[t].shift_x + bc[p].shift_x) > tol || std::fabs(bc[t].shift_y + bc[p].shift_y) > tol)
                 BAD("bc %d: partner shift is not the opposite translation", t);
+        }
+    }
+    // symmetry sides: one straight line per tag; its unit outward normal
+    std::vector<double> sym_nx(n_bc, 0.0), sym_ny(n_bc, 0.0);
+    {
+        double ext = 0;
+        for (int32_t v = 0; v < nn; v++) ext = std::max(ext, std::fabs(xy[2 * v]) + std::fabs(xy[2 * v + 1]));
+        std::vector<double> sx(n_bc, 0.0), sy(n_bc, 0.0);
+        for (int32_t e = 0; e < m->n_bedges; e++) {
+            const int32_t t = bed[e].tag;
+            if (bc[t].type != SDUGKS_BC_SYMMETRY) continue;
+            const HalfEdge &h = he[bed[e].he];
+            sx[t] += xy[2 * h.b + 1] - xy[2 * h.a + 1];
+            sy[t] += xy[2 * h.a] - xy[2 * h.b];
+        }
+        for (int32_t t = 0; t < n_bc; t++) {
+            if (bc[t].type != SDUGKS_BC_SYMMETRY) continue;
+            const double l = std::sqrt(sx[t] * sx[t] + sy[t] * sy[t]);
+            if (!(l > 0)) BAD("bc %d: symmetry side has no edges", t);
+            sym_nx[t] = sx[t] / l;
+            sym_ny[t] = sy[t] / l;
+        }
+        std::vector<double> off(n_bc, NAN);
+        for (int32_t e = 0; e < m->n_bedges; e++) {
+            const int32_t t = bed[e].tag;
+            if (bc[t].type != SDUGKS_BC_SYMMETRY) continue;
+            const HalfEdge &h = he[bed[e].he];
+            const double ex = xy[2 * h.b + 1] - xy[2 * h.a + 1], ey = xy[2 * h.a] - xy[2 * h.b];
+            const double le = std::sqrt(ex * ex + ey * ey);
+            const double d = sym_nx[t] * bed[e].mx + sym_ny[t] * bed[e].my;
+            if (std::isnan(off[t])) off[t] = d;
+            if (std::fabs(ex / le - sym_nx[t]) > 1e-9 || std::fabs(ey / le - sym_ny[t]) > 1e-9 ||
+                std::fabs(d - off[t]) > 1e-9 * (1.0 + ext))
+                BAD("bc %d: symmetry edges must lie on one straight line (edge %d)", t, e);
         }
     }
     // plain boundary faces
@@ -426,7 +460,10 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
         }
     }
     out.bcs.resize(n_bc);
-    for (int32_t t = 0; t < n_bc; t++) out.bcs[t] = {bc[t].type, bc[t].rho, bc[t].u, bc[t].v};
+    for (int32_t t = 0; t < n_bc; t++) {
+        out.bcs[t] = {bc[t].type, bc[t].rho, bc[t].u, bc[t].v};
+        if (bc[t].type == SDUGKS_BC_SYMMETRY) { out.bcs[t].u = sym_nx[t]; out.bcs[t].v = sym_ny[t]; }   // the line's normal
+    }
     out.tile_T = 0; out.n_tiles = 0;
     out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lw.clear();
     if (tiled) {

@@ -14,7 +14,7 @@ constexpr int32_t kEmptySlot = INT32_MIN;   // padding slot of a cell with fewer
 
 struct BcEntry {
     int32_t type;
-    double rho, u, v;
+    double rho, u, v;        // SYMMETRY: (u, v) = unit outward normal of the tag's line
 };
 
 // Everything the device needs, in the library's cell order.  Per-slot arrays

@@ -143,6 +143,10 @@ __device__ __forceinline__ void boundary_state_t(const double *sbc, int e, doubl
     const double type = sbc[4 * e], brho = sbc[4 * e + 1], bu = sbc[4 * e + 2], bv = sbc[4 * e + 3];
     if (type == 2.0) { rb = brho; ub = bu; vb = bv; }                // inlet / far field
     else if (type == 3.0) { rb = rho; ub = ux; vb = uy; }            // outlet
+    else if (type == 5.0) {                                          // symmetry: (bu, bv) = unit normal
+        const double un = ux * bu + uy * bv;
+        rb = rho; ub = ux - un * bu; vb = uy - un * bv;
+    }
     else { rb = rho; ub = bu; vb = bv; }                             // wall
 }
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsdugks.so")
 
 OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ENODEV = 0, -1, -2, -3, -4, -5
-BC_WALL, BC_INLET, BC_OUTLET, BC_PERIODIC = 1, 2, 3, 4
+BC_WALL, BC_INLET, BC_OUTLET, BC_PERIODIC, BC_SYMMETRY = 1, 2, 3, 4, 5
 FP64, FP32DEV = 0, 1
 MACRO_LAGGED, MACRO_CURRENT = 0, 1
 

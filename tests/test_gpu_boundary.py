@@ -30,7 +30,15 @@ CASES = {
     "couette": (lambda: meshgen.couette(4, 16), dict(nu=1e-2)),
     "inout": (lambda: meshgen.inlet_outlet_box(10, 7), dict(nu=5e-3, u0=0.05)),
     "hexagons": (lambda: meshgen.hexagon_strip(6, 4), dict(nu=5e-3)),
+    "symmetry": (lambda: meshgen.rotate(*_free_slip(), 0.6), dict(nu=1e-2)),
 }
+
+
+def _free_slip():
+    mesh, bcs = meshgen.couette(4, 10)
+    bcs = list(bcs)
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)
+    return mesh, bcs
 
 
 def colwise(a, b):
@@ -52,7 +60,7 @@ def pair(sd, oracle_mod, name, seed, **extra):
 
 
 @pytest.mark.parametrize("path", [dict(), dict(tile_cells=-1)], ids=["fused", "two_kernel"])
-@pytest.mark.parametrize("name", ["cavity", "ogrid", "couette", "inout", "hexagons"])
+@pytest.mark.parametrize("name", ["cavity", "ogrid", "couette", "inout", "hexagons", "symmetry"])
 def test_boundary_flux_matches_oracle(sd, oracle_mod, name, path):
     g, o, mesh, bcs = pair(sd, oracle_mod, name, seed=31, **path)
     for rnd in range(2):

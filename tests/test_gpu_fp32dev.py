@@ -29,6 +29,13 @@ def rel_linf(x, y):
     return np.abs(x - y).max() / np.abs(y).max()
 
 
+def _free_slip_couette():
+    mesh, bcs = meshgen.couette(5, 12)
+    bcs = list(bcs)
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)
+    return mesh, bcs
+
+
 CASES = {
     "cavity_23": (lambda: meshgen.cavity(23), dict(nu=0.001, cfl=0.5)),
     "ogrid_37x11": (lambda: meshgen.cylinder_ogrid(37, 11, seed=4), dict(nu=0.0025, cfl=0.5, u0=0.1)),
@@ -36,6 +43,7 @@ CASES = {
     "inlet_outlet_13x9": (lambda: meshgen.inlet_outlet_box(13, 9), dict(nu=0.005, cfl=0.5)),
     "couette_5x16": (lambda: meshgen.couette(5, 16), dict(nu=0.01, cfl=0.5)),
     "hybrid_ogrid_40x12": (lambda: meshgen.cylinder_ogrid(40, 12, seed=7, quad_layers=4), dict(nu=0.0025, cfl=0.5, u0=0.1)),
+    "symmetry_couette_rot": (lambda: meshgen.rotate(*_free_slip_couette(), 0.37), dict(nu=0.01, cfl=0.5)),
 }
 
 

@@ -77,6 +77,22 @@ def test_couette_full_run(sd, oracle_mod):
     assert np.abs(u - series).max() < 1e-5
 
 
+def _free_slip_couette():
+    mesh, bcs = meshgen.couette(5, 12)
+    bcs = list(bcs)
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)
+    return mesh, bcs
+
+
+def _half_channel():
+    """Upper half of a channel: inlet on the left, outlet on the right, a wall
+    on top and the centre line below as a symmetry side."""
+    mesh = meshgen.structured(np.linspace(0.0, 1.0, 14), meshgen.tanh_nodes(7, 1.0), tag_bottom=3, tag_right=1,
+                              tag_top=0, tag_left=2)
+    return mesh, [meshgen.bc(meshgen.WALL), meshgen.bc(meshgen.OUTLET), meshgen.bc(meshgen.INLET, u=0.05),
+                  meshgen.bc(meshgen.SYMMETRY)]
+
+
 def _small_cases():
     return {
         "cavity_23": (lambda: meshgen.cavity(23), dict(nu=0.001, cfl=0.5)),
@@ -89,6 +105,8 @@ def _small_cases():
                                dict(nu=0.0025, cfl=0.5, u0=0.1)),
         "hybrid_cavity_17": (lambda: (meshgen.split_some(meshgen.cavity(17)[0], 0.3, seed=4), meshgen.cavity(17)[1]),
                              dict(nu=0.001, cfl=0.5)),
+        "symmetry_couette_rot": (lambda: meshgen.rotate(*_free_slip_couette(), 0.37), dict(nu=0.01, cfl=0.5)),
+        "symmetry_half_channel": (lambda: _half_channel(), dict(nu=0.005, cfl=0.5)),
         "relabeled_cavity_11": (lambda: (meshgen.relabel(meshgen.cavity(11)[0], seed=2)[0], meshgen.cavity(11)[1]),
                                 dict(nu=0.002, cfl=0.5)),
     }

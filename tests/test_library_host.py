@@ -142,3 +142,20 @@ def test_state_bytes_scales_with_cells(lib):
     b1 = lib.state_bytes(*meshgen.cavity(32), nu=0.01)
     b2 = lib.state_bytes(*meshgen.cavity(64), nu=0.01)
     assert 3.5 < b2 / b1 < 4.5
+
+
+def test_symmetry_side_must_be_straight():
+    """A symmetry tag whose edges do not lie on one line is refused; a
+    straight (slanted) one is accepted."""
+    from paper_2007_07347_amd import sdugks
+    mesh, bcs = meshgen.inlet_outlet_box(6, 4)
+    bcs = list(bcs)
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)         # tag 0 holds both the bottom and the top side
+    with pytest.raises(sdugks.SdugksError) as ei:
+        sdugks.geometry(mesh, bcs, nu=0.01)
+    assert ei.value.code == sdugks.EINVAL
+    m2, b2 = meshgen.couette(4, 8)
+    b2 = list(b2)
+    b2[0] = meshgen.bc(meshgen.SYMMETRY)
+    m2, b2 = meshgen.rotate(m2, b2, 0.4)
+    sdugks.geometry(m2, b2, nu=0.01)
