@@ -77,7 +77,7 @@ class Oracle:
     """One simulated case.  Arrays come back cell-major in the caller's order."""
 
     def __init__(self, mesh, bcs, nu=0.0, tau=0.0, cfl=0.5, dt=0.0, rho0=1.0, u0=0.0, v0=0.0,
-                 macro=CURRENT, assembly=ASSEMBLED):
+                 macro=CURRENT, assembly=ASSEMBLED, scheme=0):
         lib = _load()
         self._keep = []
 
@@ -95,7 +95,7 @@ class Oracle:
         bval = arr([[b["rho"], b["u"], b["v"], b["shift"][0], b["shift"][1]] for b in bcs], np.float64)
         bpart = arr([b["partner"] for b in bcs], np.int32)
         prm = arr([nu, tau, cfl, dt, rho0, u0, v0], np.float64)
-        iprm = arr([macro, assembly], np.int32)
+        iprm = arr([macro, assembly, scheme], np.int32)
         err = C.create_string_buffer(256)
         self.n_cells = len(cp) - 1
         h = lib.orc_create(len(xy), _p(xy), self.n_cells, _p(cp), _p(cn), len(be), _p(be), _p(bt),

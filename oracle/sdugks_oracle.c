@@ -59,6 +59,17 @@
  *    the face; without the shift the wall slips at O(dt) and Couette flow
  *    converges at first order only);
  *  - cell centre = polygon area centroid; one midpoint per face.
+ *
+ * Scheme ORC_DUGKS (an A/B of what the paper simplifies, not the paper's own
+ * step): the original discrete unified gas kinetic scheme.  The cell carries
+ * ft = f - (dt/2) Omega; fbar+ = f + (h/2) Omega with h = dt/2 is
+ * (2tau-h)/(2tau+dt) ft + 3h/(2tau+dt) feq; faces are reconstructed at
+ * x_f - e_i h and f_face = 2tau/(2tau+h) (fbar + h/(2tau) feq_f); the cell
+ * update is ft^{n+1} = (4/3) fbar+ - (1/3) ft - dt/V F (ft+ = f + (dt/2) Omega),
+ * W^{n+1} = W^n - dt/V G.  The boundary states keep their non-equilibrium
+ * extrapolation, applied to ft (which carries the same f - feq up to the
+ * factor of the fbar+ coefficients, so fbar+_b - fbar+_c = feq_b - feq_c
+ * as in the simplified scheme).
  */
 #include "sdugks_oracle.h"
 
@@ -88,7 +99,8 @@ struct orc_case {
     double *bcv;                /* rho, u, v, sx, sy */
     /* parameters */
     double dt, tau, hmin, a, b, c1, lam;
-    int macro_mode, assembly;
+    double dtr, fb_b, fb_c1;    /* face step: reconstruction time, dt/(2tau) and 2tau/(2tau+dt) of Eq. f_t_n+1 */
+    int macro_mode, assembly, scheme;
     /* state */
     double *f, *W, *G;          /* [nc][9], [nc][3], [nc][3] */
     double *snapU, *snapV;
@@ -348,8 +360,19 @@ orc_case *orc_create(int n_nodes, const double *xy, int nc, const int *cptr, con
     o->b = dt / (2.0 * tau);
     o->c1 = 2.0 * tau / (2.0 * tau + dt);
     o->lam = dt / tau;
+    o->dtr = dt; o->fb_b = o->b; o->fb_c1 = o->c1;
     o->macro_mode = iprm[0];
     o->assembly = iprm[1];
+    o->scheme = iprm[2];
+    if (o->scheme == ORC_DUGKS) {
+        /* the original scheme: faces at half a step, h = dt/2, and the cell
+         * variable ft = f - (dt/2) Omega; fbar+ = f + (h/2) Omega written in ft */
+        double h = 0.5 * dt;
+        if (o->macro_mode != ORC_CURRENT) FAIL("the original scheme has no lagged macroscopic flux");
+        o->a = (2.0 * tau - h) / (2.0 * tau + dt);
+        o->b = 3.0 * h / (2.0 * tau + dt);
+        o->dtr = h; o->fb_b = h / (2.0 * tau); o->fb_c1 = 2.0 * tau / (2.0 * tau + h);
+    } else if (o->scheme != ORC_SDUGKS) FAIL("unknown scheme %d", o->scheme);
 
     /* state: uniform equilibrium (rho0, u0, v0), G = 0 */
     o->f = xcalloc((size_t)nc * 9, 8); o->W = xcalloc((size_t)nc * 3, 8); o->G = xcalloc((size_t)nc * 3, 8);
@@ -405,9 +428,21 @@ void orc_faces(const orc_case *o, int *ow, int *nb, int *bcid, double *lnx, doub
     }
 }
 
+/* the original scheme keeps ft = f - (dt/2) Omega = (1 + dt/2tau) f - (dt/2tau) feq(W) per cell */
+static void to_tilde(const orc_case *o, const double *f, const double *W, double *ft, int inverse)
+{
+    double k = o->dt / (2.0 * o->tau), fe[9];
+    for (int c = 0; c < o->nc; c++) {
+        feq_of_W(&W[3 * c], fe);
+        for (int i = 0; i < 9; i++)
+            ft[9 * c + i] = inverse ? (f[9 * c + i] + k * fe[i]) / (1.0 + k) : (1.0 + k) * f[9 * c + i] - k * fe[i];
+    }
+}
+
 void orc_set_state(orc_case *o, const double *f, const double *W, const double *G)
 {
-    memcpy(o->f, f, sizeof(double) * 9 * o->nc);
+    if (o->scheme == ORC_DUGKS) to_tilde(o, f, W, o->f, 0);
+    else memcpy(o->f, f, sizeof(double) * 9 * o->nc);
     memcpy(o->W, W, sizeof(double) * 3 * o->nc);
     memcpy(o->G, G, sizeof(double) * 3 * o->nc);
     for (int c = 0; c < o->nc; c++) { o->snapU[c] = W[3 * c + 1] / W[3 * c]; o->snapV[c] = W[3 * c + 2] / W[3 * c]; }
@@ -415,7 +450,10 @@ void orc_set_state(orc_case *o, const double *f, const double *W, const double *
 
 void orc_get_state(const orc_case *o, double *f, double *W, double *G)
 {
-    if (f) memcpy(f, o->f, sizeof(double) * 9 * o->nc);
+    if (f) {
+        if (o->scheme == ORC_DUGKS) to_tilde(o, o->f, o->W, f, 1);
+        else memcpy(f, o->f, sizeof(double) * 9 * o->nc);
+    }
     if (W) memcpy(W, o->W, sizeof(double) * 3 * o->nc);
     if (G) memcpy(G, o->G, sizeof(double) * 3 * o->nc);
 }
@@ -525,8 +563,8 @@ static void prepare(orc_case *o, int cramer)
  * (px,py) is the face midpoint in c's frame */
 static double reconstruct(const orc_case *o, int c, int i, double px, double py)
 {
-    double rx = px - EX[i] * o->dt - o->cx[c];
-    double ry = py - EY[i] * o->dt - o->cy[c];
+    double rx = px - EX[i] * o->dtr - o->cx[c];
+    double ry = py - EY[i] * o->dtr - o->cy[c];
     return o->fbp[9 * c + i] + rx * o->sig[18 * c + 2 * i] + ry * o->sig[18 * c + 2 * i + 1];
 }
 
@@ -540,8 +578,8 @@ static void face_flux(const orc_case *o, int f, double *fbar, double *fface, dou
             /* incoming: the boundary state's fbar+ carried to the foot point x_f - e_i dt
              * with the adjacent cell's gradient (Eq. fbpsource about the face) */
             fbar[i] = (s >= 0) ? reconstruct(o, co, i, o->xm[f], o->ym[f])
-                               : o->ghost[9 * f + i] - o->dt * (EX[i] * o->sig[18 * co + 2 * i]
-                                                               + EY[i] * o->sig[18 * co + 2 * i + 1]);
+                               : o->ghost[9 * f + i] - o->dtr * (EX[i] * o->sig[18 * co + 2 * i]
+                                                                + EY[i] * o->sig[18 * co + 2 * i + 1]);
         } else {
             double ro = reconstruct(o, co, i, o->xm[f], o->ym[f]);
             double rn = reconstruct(o, cn, i, o->xm[f] + o->tx[f], o->ym[f] + o->ty[f]);
@@ -555,7 +593,7 @@ static void face_flux(const orc_case *o, int f, double *fbar, double *fface, dou
     gam[0] = gam[1] = gam[2] = 0;
     for (int i = 0; i < 9; i++) {
         double s = EX[i] * o->lnx[f] + EY[i] * o->lny[f];
-        fface[i] = o->c1 * (fbar[i] + o->b * fe[i]);
+        fface[i] = o->fb_c1 * (fbar[i] + o->fb_b * fe[i]);
         phi[i] = s * fface[i];
         gam[0] += phi[i]; gam[1] += EX[i] * phi[i]; gam[2] += EY[i] * phi[i];
     }
@@ -609,6 +647,13 @@ static void one_step(orc_case *o)
         double k = o->dt / o->area[c];
         const double *Gs = (o->macro_mode == ORC_LAGGED) ? &o->G[3 * c] : &o->Gn[3 * c];
         for (int m = 0; m < 3; m++) o->W[3 * c + m] = o->W[3 * c + m] - k * Gs[m];
+        if (o->scheme == ORC_DUGKS) {
+            /* ft^{n+1} = ft+ - dt/V F with ft+ = f + (dt/2) Omega = (4/3) fbar+ - (1/3) ft */
+            for (int i = 0; i < 9; i++)
+                o->f[9 * c + i] = (4.0 / 3.0) * o->fbp[9 * c + i] - (1.0 / 3.0) * o->f[9 * c + i] - k * o->F[9 * c + i];
+            for (int m = 0; m < 3; m++) o->G[3 * c + m] = o->Gn[3 * c + m];
+            continue;
+        }
         feq_of_W(&o->W[3 * c], fe);
         for (int i = 0; i < 9; i++)
             o->f[9 * c + i] = (o->f[9 * c + i] - k * o->F[9 * c + i] + o->lam * fe[i]) / (1.0 + o->lam);

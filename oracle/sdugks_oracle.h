@@ -28,9 +28,10 @@ typedef struct orc_case orc_case;
 enum { ORC_WALL = 1, ORC_INLET = 2, ORC_OUTLET = 3, ORC_PERIODIC = 4, ORC_SYMMETRY = 5 };
 enum { ORC_LAGGED = 0, ORC_CURRENT = 1 };     /* time level of the macroscopic flux */
 enum { ORC_ASSEMBLED = 0, ORC_BRUTE = 1 };    /* assembly mode */
+enum { ORC_SDUGKS = 0, ORC_DUGKS = 1 };       /* the paper's simplified step, or the original half-step scheme */
 
 /* prm: {nu, tau, cfl, dt, rho0, u0, v0}; nu or tau > 0 (tau wins), dt > 0 overrides cfl.
- * iprm: {macro_mode, assembly_mode}.
+ * iprm: {macro_mode, assembly_mode, scheme}.
  * bc_val: per BC {rho, u, v, shift_x, shift_y}.
  * Returns NULL on error, with a message in err (256 bytes). */
 orc_case *orc_create(int n_nodes, const double *node_xy, int n_cells, const int *cell_ptr,

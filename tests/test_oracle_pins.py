@@ -508,3 +508,71 @@ def test_symmetry_brute_force_equals_assembled(oracle_mod):
         res.append(o.state())
     for a, b in zip(res[0], res[1]):
         assert np.abs(a - b).max() <= 1e-14 * max(1.0, np.abs(b).max())
+
+
+# ---- the original (half-step) scheme, the A/B of the paper's simplification
+
+def test_original_scheme_state_round_trip_and_conservation(oracle_mod):
+    """The original scheme keeps ft = f - (dt/2) Omega internally: f survives
+    set/get unchanged, and mass is conserved to rounding on a periodic mesh."""
+    mesh, bcs = meshgen.jittered_periodic_triangles(10, seed=2)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5, scheme=1)
+    f, _, _ = meshgen.random_state(o.n_cells, seed=3)
+    W = np.c_[f.sum(1), f @ EX, f @ EY]
+    o.set_state(f, W)
+    f2, W2, _ = o.state()
+    assert np.abs(f2 - f).max() <= 1e-15 and np.array_equal(W2, W)
+    m0 = o.mass()
+    o.step(300)
+    assert abs(o.mass() - m0) <= 1e-14 * m0
+    # a uniform equilibrium stays put
+    n = o.n_cells
+    fe = np.tile(oracle_mod.feq(1.05, 0.03, -0.02), (n, 1))
+    o.set_state(fe, np.tile([1.05, 1.05 * 0.03, -1.05 * 0.02], (n, 1)))
+    o.step(200)
+    assert np.abs(o.state()[0] - fe).max() <= 1e-14
+
+
+def test_original_scheme_couette_and_viscosity(oracle_mod):
+    """The original scheme also reproduces steady Couette flow exactly and
+    decays a shear wave at nu k^2 (64^2, within 1e-3)."""
+    mesh, bcs = meshgen.couette(4, 8)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5, scheme=1)
+    g = o.geometry()
+    n = o.n_cells
+    fe = np.array([oracle_mod.feq(1.0, 0.1 * y, 0.0) for y in g["cy"]])
+    o.set_state(fe, np.c_[np.ones(n), 0.1 * g["cy"], np.zeros(n)])
+    o.step(5000)
+    _, u, v = o.macros()
+    assert np.abs(u - 0.1 * g["cy"]).max() <= 1e-12 and np.abs(v).max() <= 1e-12
+    nb = 64
+    mesh, bcs = meshgen.periodic_box(nb, nb)
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.0025, cfl=0.5, scheme=1)
+    g = o.geometry()
+    k = 2 * math.pi
+    u = 0.01 * np.sin(k * g["cy"])
+    o.set_state(np.array([oracle_mod.feq(1.0, x, 0.0) for x in u]), np.c_[np.ones(nb * nb), u, np.zeros(nb * nb)])
+    steps = int(20.0 / o.dt)
+    o.step(steps)
+    _, uu, _ = o.macros()
+    rate = -math.log(2 * np.mean(uu * np.sin(k * g["cy"])) / 0.01) / (steps * o.dt)
+    assert abs(rate / (0.0025 * k * k) - 1.0) <= 1e-3
+
+
+def test_original_scheme_brute_force_equals_assembled(oracle_mod):
+    mesh, bcs = _tiny_cases()[3]
+    res = []
+    for assembly in (0, 1):
+        o = oracle_mod.Oracle(mesh, bcs, nu=0.02, cfl=0.5, assembly=assembly, scheme=1)
+        f, W, _ = meshgen.random_state(o.n_cells, seed=43)
+        o.set_state(f, W)
+        o.step(50)
+        res.append(o.state())
+    for a, b in zip(res[0], res[1]):
+        assert np.abs(a - b).max() <= 1e-14 * max(1.0, np.abs(b).max())
+
+
+def test_original_scheme_has_no_lagged_flux(oracle_mod):
+    mesh, bcs = meshgen.cavity(4)
+    with pytest.raises(ValueError):
+        oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5, scheme=1, macro=0)
