@@ -68,6 +68,14 @@ enum { SDUGKS_FP64 = 0, SDUGKS_FP32DEV = 1 };
  * step's (LAGGED; stable only for dt below about 3 tau). */
 enum { SDUGKS_MACRO_LAGGED = 0, SDUGKS_MACRO_CURRENT = 1 };
 
+/* SIMPLIFIED: the paper's step (Section II summary).  ORIGINAL: the discrete
+ * unified gas kinetic scheme it simplifies, for comparison -- faces at half a
+ * step (h = dt/2, reconstruction at x_f - e_i h, f_face = 2tau/(2tau+h)
+ * (fbar + h/(2tau) feq_f)), the cell variable ft = f - (dt/2) Omega and the
+ * explicit update ft^{n+1} = (4/3) fbar+ - (1/3) ft - dt/V F.  f crossing the
+ * ABI is always f.  ORIGINAL needs the fused step and the CURRENT flux. */
+enum { SDUGKS_SCHEME_SIMPLIFIED = 0, SDUGKS_SCHEME_ORIGINAL = 1 };
+
 /* Raw mesh: polygons of 3..8 nodes, counter-clockwise.  Every edge of a cell
  * that no other cell shares must appear once in bedge_nodes (either order). */
 typedef struct {
@@ -104,6 +112,7 @@ typedef struct {
                                      polygons of more than four faces or more than 64 boundary-condition
                                      entries always take the two-kernel step) */
     int32_t block_threads;        /* threads per workgroup of the fused step: 64, 128 or 256 (0 = default) */
+    int32_t scheme;               /* SDUGKS_SCHEME_SIMPLIFIED (default) or SDUGKS_SCHEME_ORIGINAL */
 } sdugks_params;
 
 typedef struct sdugks_s sdugks_t;

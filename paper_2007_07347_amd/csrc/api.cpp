@@ -106,7 +106,7 @@ struct sdugks_s {
     int cur = 0;                 // index of the current (input) state buffers
     int64_t step = 0;
     bool diverged = false;
-    int precision = SDUGKS_FP64, macro = SDUGKS_MACRO_CURRENT;
+    int precision = SDUGKS_FP64, macro = SDUGKS_MACRO_CURRENT, scheme = SDUGKS_SCHEME_SIMPLIFIED;
     double rho0 = 1.0;
     int block = 256;
     DevMesh dm{};
@@ -160,6 +160,10 @@ int check_prm(const sdugks_params *prm)
         return fail(SDUGKS_EINVAL, "precision must be SDUGKS_FP64 or SDUGKS_FP32DEV");
     if (prm->macro_flux != SDUGKS_MACRO_CURRENT && prm->macro_flux != SDUGKS_MACRO_LAGGED)
         return fail(SDUGKS_EINVAL, "macro_flux must be SDUGKS_MACRO_CURRENT or SDUGKS_MACRO_LAGGED");
+    if (prm->scheme != SDUGKS_SCHEME_SIMPLIFIED && prm->scheme != SDUGKS_SCHEME_ORIGINAL)
+        return fail(SDUGKS_EINVAL, "scheme must be SDUGKS_SCHEME_SIMPLIFIED or SDUGKS_SCHEME_ORIGINAL");
+    if (prm->scheme == SDUGKS_SCHEME_ORIGINAL && prm->macro_flux != SDUGKS_MACRO_CURRENT)
+        return fail(SDUGKS_EINVAL, "the original scheme has no lagged macroscopic flux");
     if (!(prm->rho0 > 0)) return fail(SDUGKS_EINVAL, "rho0 must be positive");
     if (prm->block_threads != 0 && prm->block_threads != 64 && prm->block_threads != 128 && prm->block_threads != 256)
         return fail(SDUGKS_EINVAL, "block_threads must be 0, 64, 128 or 256");
@@ -175,6 +179,8 @@ int build(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdug
     if (rc) return fail(rc, "mesh: " + err);
     if (prm->precision == SDUGKS_FP32DEV && mb.n_tiles == 0)
         return fail(SDUGKS_EINVAL, "SDUGKS_FP32DEV needs the fused step (polygons of at most four faces, at most 64 boundary-condition entries, tile_cells >= 0)");
+    if (prm->scheme == SDUGKS_SCHEME_ORIGINAL && mb.n_tiles == 0)
+        return fail(SDUGKS_EINVAL, "SDUGKS_SCHEME_ORIGINAL needs the fused step (polygons of at most four faces, at most 64 boundary-condition entries, tile_cells >= 0)");
     return SDUGKS_OK;
 }
 
@@ -304,6 +310,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     h->block = prm->block_threads ? prm->block_threads : 256;
     h->precision = prm->precision;
     h->macro = prm->macro_flux;
+    h->scheme = prm->scheme;
     h->rho0 = prm->rho0;
     h->L = make_layout(h->mb, prm->precision);
     const Layout &L = h->L;
@@ -457,6 +464,13 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     d.c1 = 2.0 * tau / (2.0 * tau + dt);
     d.lam = dt / tau;
     d.inv1l = 1.0 / (1.0 + d.lam);
+    d.dtr = dt; d.fb = d.b; d.fc1 = d.c1; d.scheme = h->scheme;
+    if (h->scheme == SDUGKS_SCHEME_ORIGINAL) {
+        const double hh = 0.5 * dt;
+        d.a = (2.0 * tau - hh) / (2.0 * tau + dt);
+        d.b = 3.0 * hh / (2.0 * tau + dt);
+        d.dtr = hh; d.fb = hh / (2.0 * tau); d.fc1 = 2.0 * tau / (2.0 * tau + hh);
+    }
     d.dt = dt;
     // initial state: uniform equilibrium, G = 0, snapshot = initial velocity
     {
@@ -473,11 +487,34 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     return SDUGKS_OK;
 }
 
+// The original scheme stores ft = f - (dt/2) Omega = (1 + k) f - k feq(W),
+// k = dt/(2 tau); inverse f = (ft + k feq(W)) / (1 + k).  Caller order, in place.
+static void tilde_convert(double *f, const double *W, size_t nc, double k, bool inverse)
+{
+    for (size_t c = 0; c < nc; c++) {
+        const double r = W[3 * c], u = W[3 * c + 1] / r, v = W[3 * c + 2] / r;
+        for (int i = 0; i < 9; i++) {
+            const double fe = feq_host(i, r, u, v);
+            double &x = f[c * 9 + i];
+            x = inverse ? (x + k * fe) / (1.0 + k) : (1.0 + k) * x - k * fe;
+        }
+    }
+}
+
 int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double *G)
 {
     if (!h) return fail(SDUGKS_EINVAL, "null handle");
     HIPCHK(hipSetDevice(h->device));
     const size_t nc = h->mb.nc, np = h->L.np;
+    std::vector<double> ft;
+    if (f && h->scheme == SDUGKS_SCHEME_ORIGINAL) {
+        std::vector<double> Wc(3 * nc);
+        if (W) std::copy(W, W + 3 * nc, Wc.begin());
+        else if (int r0 = sdugks_get_state(h, nullptr, Wc.data(), nullptr)) return r0;
+        ft.assign(f, f + 9 * nc);
+        tilde_convert(ft.data(), Wc.data(), nc, h->mb.dt / (2.0 * h->mb.tau), false);
+        f = ft.data();
+    }
     const Layout &L = h->L;
     std::vector<double> buf(9 * np, 0.0);
     auto put = [&](const double *src, int rows, size_t off) -> int {
@@ -552,6 +589,11 @@ int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G)
         return rc;
     }
     if (W && (rc = get(W, 3, L.off_W[h->cur]))) return rc;
+    if (f && h->scheme == SDUGKS_SCHEME_ORIGINAL) {
+        std::vector<double> Wc(3 * nc);
+        if ((rc = get(Wc.data(), 3, L.off_W[h->cur]))) return rc;
+        tilde_convert(f, Wc.data(), nc, h->mb.dt / (2.0 * h->mb.tau), true);
+    }
     if (G) {
         if (h->macro == SDUGKS_MACRO_LAGGED) { if ((rc = get(G, 3, L.off_G[h->cur]))) return rc; }
         else std::fill(G, G + 3 * nc, 0.0);

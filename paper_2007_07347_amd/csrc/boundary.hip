@@ -91,9 +91,9 @@ __global__ void __launch_bounds__(64) k_boundary_flux(DevMesh m, DevState s, Dev
 #pragma unroll
     for (int i = 0; i < 9; i++) {
         const double sn = kEx[i] * ln.x + kEy[i] * ln.y;
-        const double inner = fbp[i] + (rs.x - m.dt * kEx[i]) * sx[i] + (rs.y - m.dt * kEy[i]) * sy[i];
+        const double inner = fbp[i] + (rs.x - m.dtr * kEx[i]) * sx[i] + (rs.y - m.dtr * kEy[i]) * sy[i];
         const double gb = (feq_one(kW[i], kEx[i], kEy[i], rb, ub, vb) - fe[i]) + fbp[i];
-        fbar[i] = sn >= 0.0 ? inner : gb - m.dt * (kEx[i] * sx[i] + kEy[i] * sy[i]);
+        fbar[i] = sn >= 0.0 ? inner : gb - m.dtr * (kEx[i] * sx[i] + kEy[i] * sy[i]);
         rf += fbar[i];
         mx += kEx[i] * fbar[i];
         my += kEy[i] * fbar[i];
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(64) k_boundary_flux(DevMesh m, DevState s, Dev
 #pragma unroll
     for (int i = 0; i < 9; i++) {
         const double sn = kEx[i] * ln.x + kEy[i] * ln.y;
-        const double phi = sn * (m.c1 * (fbar[i] + m.b * feq_one(kW[i], kEx[i], kEy[i], rf, uf, vf)));
+        const double phi = sn * (m.fc1 * (fbar[i] + m.fb * feq_one(kW[i], kEx[i], kEy[i], rf, uf, vf)));
         g0 += phi;
         g1 += kEx[i] * phi;
         g2 += kEy[i] * phi;

@@ -27,6 +27,11 @@ struct DevMesh {
     const DevBC *bcs;                   // [n_bc]
     double a, b, c1, lam, dt;           // (2tau-dt)/2tau, dt/2tau, 2tau/(2tau+dt), dt/tau, dt
     double inv1l;                       // 1 / (1 + dt/tau)
+    // face step: reconstruction time, and the coefficients of the face
+    // distribution f_face = fc1 (fbar + fb feq_f); (dt, b, c1) for the paper's
+    // scheme, (dt/2, dt/4tau, 2tau/(2tau+dt/2)) for the original one
+    double dtr, fb, fc1;
+    int32_t scheme;                     // 0 the paper's scheme, 1 the original one
     // FP32 copies of the face geometry for the deviation form (null otherwise)
     const float2 *ln32, *rs32, *ro32;
     double rho0;                        // offset of the deviation form: f = w_i rho0 + stored value

@@ -180,7 +180,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         lw = tl.lw + (size_t)t * D * P1;
         gln = m.ln; grs = m.rs; gro = m.ro;
     }
-    const R ra = (R)m.a, rb_ = (R)m.b, rc1 = (R)m.c1, rdt = (R)m.dt;
+    // fbar+ from the cell variable (phase 1); the face step: reconstruction
+    // time and the coefficients of the face distribution (phase 3)
+    const R ra = (R)m.a, rb_ = (R)m.b, rc1 = (R)m.fc1, rbf = (R)m.fb, rdt = (R)m.dtr;
     // ---- requests of all phases, in this order: the local cell ids; the
     // inputs of phases 2 and 3 (adjacency, weights, face geometry, boundary
     // table), which need nothing loaded first; then the phase-1 state at the
@@ -355,7 +357,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             } else {
                 fe = feq_c<EX, EY>((R)cW[i], rf, uf, vf, uu);
             }
-            phi[i] = sn * (rc1 * (fbar[i] + rb_ * fe));
+            phi[i] = sn * (rc1 * (fbar[i] + rbf * fe));
             g0s += (double)phi[i];
             if constexpr (EX != 0) g1s += cmul<EX>((double)phi[i]);
             if constexpr (EY != 0) g2s += cmul<EY>((double)phi[i]);
@@ -395,15 +397,28 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         const double F0 = sl3 == 0 ? phi[0] : (sl3 == 1 ? phi[1] : (sl3 == 2 ? phi[2] : phi[3]));
         const double F1 = sl3 == 0 ? phi[4] : (sl3 == 1 ? phi[5] : (sl3 == 2 ? phi[6] : phi[7]));
         const double base = 1.0 - 1.5 * uun;
-        const double fe0 = w0 * rn * (base + eu0 * (3.0 + 4.5 * eu0)) - (DEV ? w0 * m.rho0 : 0.0);
-        const double fe1 = w1 * rn * (base + eu1 * (3.0 + 4.5 * eu1)) - (DEV ? w1 * m.rho0 : 0.0);
-        const double v0 = (fo0 - dtv * F0 + lam * fe0) * inv, v1 = (fo1 - dtv * F1 + lam * fe1) * inv;
         const int i0 = sl3, i1 = sl3 + 4;
+        double v0, v1;
+        if (m.scheme == 0) {
+            const double fe0 = w0 * rn * (base + eu0 * (3.0 + 4.5 * eu0)) - (DEV ? w0 * m.rho0 : 0.0);
+            const double fe1 = w1 * rn * (base + eu1 * (3.0 + 4.5 * eu1)) - (DEV ? w1 * m.rho0 : 0.0);
+            v0 = (fo0 - dtv * F0 + lam * fe0) * inv;
+            v1 = (fo1 - dtv * F1 + lam * fe1) * inv;
+        } else {
+            // the original scheme: ft^{n+1} = (4/3) fbar+ - (1/3) ft - dt/V F
+            v0 = (4.0 / 3.0) * (double)sfbp[lc * 9 + i0] - (1.0 / 3.0) * fo0 - dtv * F0;
+            v1 = (4.0 / 3.0) * (double)sfbp[lc * 9 + i1] - (1.0 / 3.0) * fo1 - dtv * F1;
+        }
         if constexpr (DEV) { s.fo32[(size_t)i0 * np + g] = (float)v0; s.fo32[(size_t)i1 * np + g] = (float)v1; }
         else { s.fo[(size_t)i0 * np + g] = v0; s.fo[(size_t)i1 * np + g] = v1; }
         if (sl3 == 0) {
-            const double fe2 = feq_c<cEx[8], cEy[8]>(cW[8], rn, un, vn, uun) - (DEV ? cW[8] * m.rho0 : 0.0);
-            const double v2 = (fo2 - dtv * (double)phi[8] + lam * fe2) * inv;
+            double v2;
+            if (m.scheme == 0) {
+                const double fe2 = feq_c<cEx[8], cEy[8]>(cW[8], rn, un, vn, uun) - (DEV ? cW[8] * m.rho0 : 0.0);
+                v2 = (fo2 - dtv * (double)phi[8] + lam * fe2) * inv;
+            } else {
+                v2 = (4.0 / 3.0) * (double)sfbp[lc * 9 + 8] - (1.0 / 3.0) * fo2 - dtv * (double)phi[8];
+            }
             if constexpr (DEV) s.fo32[(size_t)8 * np + g] = (float)v2;
             else s.fo[(size_t)8 * np + g] = v2;
         }

@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ENODEV = 0, -1, -2, -3, -4, -5
 BC_WALL, BC_INLET, BC_OUTLET, BC_PERIODIC, BC_SYMMETRY = 1, 2, 3, 4, 5
 FP64, FP32DEV = 0, 1
 MACRO_LAGGED, MACRO_CURRENT = 0, 1
+SCHEME_SIMPLIFIED, SCHEME_ORIGINAL = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'` "
@@ -39,7 +40,7 @@ class Params(C.Structure):
     _fields_ = [("nu", C.c_double), ("tau", C.c_double), ("cfl", C.c_double), ("dt", C.c_double),
                 ("rho0", C.c_double), ("u0", C.c_double), ("v0", C.c_double), ("precision", C.c_int32),
                 ("macro_flux", C.c_int32), ("reorder", C.c_int32), ("residual_interval", C.c_int32),
-                ("tile_cells", C.c_int32), ("block_threads", C.c_int32)]
+                ("tile_cells", C.c_int32), ("block_threads", C.c_int32), ("scheme", C.c_int32)]
 
 
 _lib = C.CDLL(LIB_PATH)
@@ -95,7 +96,7 @@ class _Inputs:
 
     def __init__(self, mesh, bcs, nu=0.0, tau=0.0, cfl=0.5, dt=0.0, rho0=1.0, u0=0.0, v0=0.0,
                  precision=FP64, macro=MACRO_CURRENT, reorder=True, residual_interval=1000, tile_cells=0,
-                 block_threads=0):
+                 block_threads=0, scheme=0):
         self.xy = np.ascontiguousarray(mesh["node_xy"], dtype=np.float64)
         self.cp = np.ascontiguousarray(mesh["cell_ptr"], dtype=np.int32)
         self.cn = np.ascontiguousarray(mesh["cell_nodes"], dtype=np.int32)
@@ -109,7 +110,7 @@ class _Inputs:
             self.bcs[k] = BC(b["type"], b.get("partner", -1), b.get("rho", 1.0), b.get("u", 0.0), b.get("v", 0.0),
                              b.get("shift", (0.0, 0.0))[0], b.get("shift", (0.0, 0.0))[1])
         self.prm = Params(nu, tau, cfl, dt, rho0, u0, v0, precision, macro, 1 if reorder else 0, residual_interval,
-                          tile_cells, block_threads)
+                          tile_cells, block_threads, scheme)
         self.n_cells = len(self.cp) - 1
 
     def args(self):

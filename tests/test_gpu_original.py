@@ -1,0 +1,120 @@
+"""The original (half-step) discrete unified gas kinetic scheme, the
+comparison the paper's simplification is measured against: the HIP fused
+step in SDUGKS_SCHEME_ORIGINAL against the oracle's original-scheme step,
+element by element on the same seeded states (FP64 within 1e-12 relative,
+FP32 deviation storage within 2e-6 after 40 steps), its boundary fluxes, a
+batch mixing both schemes, and the refusals."""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_07347_amd import sdugks
+    return sdugks
+
+
+def rel_linf(x, y):
+    return np.abs(x - y).max() / np.abs(y).max()
+
+
+def _free_slip():
+    mesh, bcs = meshgen.couette(5, 12)
+    bcs = list(bcs)
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)
+    return meshgen.rotate(mesh, bcs, 0.37)
+
+
+CASES = {
+    "cavity_23": (lambda: meshgen.cavity(23), dict(nu=0.001, cfl=0.5)),
+    "ogrid_37x11": (lambda: meshgen.cylinder_ogrid(37, 11, seed=4), dict(nu=0.0025, cfl=0.5, u0=0.1)),
+    "hybrid_ogrid_40x12": (lambda: meshgen.cylinder_ogrid(40, 12, seed=7, quad_layers=4),
+                           dict(nu=0.0025, cfl=0.5, u0=0.1)),
+    "periodic_tri_9": (lambda: meshgen.jittered_periodic_triangles(9, seed=6), dict(nu=0.004, cfl=0.5)),
+    "inlet_outlet_13x9": (lambda: meshgen.inlet_outlet_box(13, 9), dict(nu=0.005, cfl=0.5)),
+    "symmetry_couette_rot": (_free_slip, dict(nu=0.01, cfl=0.5)),
+}
+PATHS = {"fused": dict(tile_cells=0), "fused_t16_b64": dict(tile_cells=16, block_threads=64)}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_original_scheme_window(sd, oracle_mod, name, path):
+    build, kw = CASES[name]
+    mesh, bcs = build()
+    g = sd.Solver(mesh, bcs, scheme=sd.SCHEME_ORIGINAL, **kw, **PATHS[path])
+    o = oracle_mod.Oracle(mesh, bcs, scheme=1, **kw)
+    f, _, _ = meshgen.random_state(o.n_cells, seed=29)
+    W = np.c_[f.sum(1), f @ EX, f @ EY]
+    g.set_state(f, W)
+    o.set_state(f, W)
+    for n in (1, 39):
+        g.step(n)
+        o.step(n)
+        fg, Wg, _ = g.state()
+        fo, Wo, _ = o.state()
+        errs = (rel_linf(fg, fo), rel_linf(Wg[:, 0], Wo[:, 0]), rel_linf(Wg[:, 1:], Wo[:, 1:]))
+        print(name, path, n, errs, flush=True)
+        assert max(errs) <= 1e-12
+    bg, _ = g.boundary_flux()
+    bo, _ = o.boundary_flux()
+    if len(bo):
+        scale = np.maximum(np.abs(bo).max(0), 1e-300)
+        assert (np.abs(bg - bo).max(0) / scale).max() <= 1e-12
+
+
+def test_original_scheme_fp32_deviation(sd, oracle_mod):
+    mesh, bcs = meshgen.cylinder_ogrid(37, 11, seed=4)
+    kw = dict(nu=0.0025, cfl=0.5, u0=0.1)
+    g = sd.Solver(mesh, bcs, scheme=sd.SCHEME_ORIGINAL, precision=sd.FP32DEV, **kw)
+    o = oracle_mod.Oracle(mesh, bcs, scheme=1, **kw)
+    f, _, _ = meshgen.random_state(o.n_cells, seed=30, amp=0.02)
+    W = np.c_[f.sum(1), f @ EX, f @ EY]
+    g.set_state(f, W)
+    fg0, Wg0, _ = g.state()
+    o.set_state(fg0, Wg0)
+    g.step(40)
+    o.step(40)
+    fg, Wg, _ = g.state()
+    fo, Wo, _ = o.state()
+    assert rel_linf(fg, fo) <= 2e-6 and rel_linf(Wg, Wo) <= 2e-6
+
+
+def test_batch_mixes_both_schemes(sd):
+    specs = [(meshgen.cavity(20), dict(nu=1e-3)),
+             (meshgen.cavity(20), dict(nu=1e-3, scheme=sd.SCHEME_ORIGINAL)),
+             (meshgen.cylinder_ogrid(40, 12, seed=7), dict(nu=2.5e-3, u0=0.1, scheme=sd.SCHEME_ORIGINAL))]
+    alone, batched = [], []
+    for k, ((mesh, bcs), kw) in enumerate(specs):
+        for dst in (alone, batched):
+            s = sd.Solver(mesh, bcs, cfl=0.5, **kw)
+            f, _, _ = meshgen.random_state(s.n_cells, seed=50 + k, amp=0.01)
+            s.set_state(f, np.c_[f.sum(1), f @ EX, f @ EY])
+            dst.append(s)
+    for s in alone:
+        s.step(9)
+    b = sd.Batch(batched)
+    b.step(9)
+    for sa, sb in zip(alone, batched):
+        for x, y in zip(sa.state(), sb.state()):
+            assert np.array_equal(x, y)
+    b.close()
+
+
+def test_original_scheme_refusals(sd):
+    mesh, bcs = meshgen.cavity(8)
+    with pytest.raises(sd.SdugksError):
+        sd.Solver(mesh, bcs, nu=0.01, scheme=sd.SCHEME_ORIGINAL, macro=sd.MACRO_LAGGED)
+    with pytest.raises(sd.SdugksError):
+        sd.Solver(mesh, bcs, nu=0.01, scheme=sd.SCHEME_ORIGINAL, tile_cells=-1)
+    with pytest.raises(sd.SdugksError):
+        sd.Solver(*meshgen.hexagon_strip(4, 3), nu=0.01, scheme=sd.SCHEME_ORIGINAL)
