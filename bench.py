@@ -13,8 +13,10 @@ instances one after another; the continuous-batching serving loop on a finite
 seeded request trace with p50/p99 time-to-steady, against the per-case FP64
 loop; steady drag, lift, stagnation pressure and recirculation length of the
 circular cylinder at Re = 10, 20, 40 and its Strouhal number and mean drag at
-Re = 60, 80, 100; the HBM roofline of the step kernel; and
-the CPU oracle timed on a bounded sample of the headline workload.
+Re = 60, 80, 100; the original half-step DUGKS against the simplified
+scheme (cost per step on the headline cavity, shear-wave accuracy, largest
+stable CFL against Dt/tau); the HBM roofline of the step kernel; and the CPU
+oracle timed on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
     python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
@@ -84,6 +86,10 @@ def copy_calibration(mb):
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def time_steps(step, n, stream=None):
@@ -208,6 +214,7 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
         s, r = cylinder.run_steady(sdugks, mesh, bcs, re, tol=tol, interval=2000, cfl=0.5)
         L = cylinder.recirculation_length(s, mesh, bcs, nu=0.1 / re, cfl=0.5, u0=0.1)
         th, cp = cylinder.pressure_coefficient(s, mesh, bcs)
+        progress(f"cylinder Re {re}: {r['steps']} steps, C_d {r['Cd']:.4f}")
         rows.append({"Re": re, "steps": r["steps"], "residual": float(f"{r['residual']:.3g}"),
                      "Cd": round(float(r["Cd"]), 4), "Cl": float(f"{r['Cl']:.2g}"), "L_over_R": round(2.0 * L, 3),
                      "Cp_front": round(float(cp[np.argmin(np.abs(th - math.pi))]), 3),
@@ -220,6 +227,7 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
         t0 = time.perf_counter()
         s, r = cylinder.run_shedding(sdugks, mesh, bcs, re, t_transient=1500.0, t_sample=500.0, cfl=0.5, kick=0.2)
         s.close()
+        progress(f"cylinder Re {re}: St {r['St']:.4f}")
         unsteady.append({"Re": re, "St": round(r["St"], 4), "Cd_mean": round(r["Cd_mean"], 4),
                          "Cl_amp": round(r["Cl_amp"], 4), "steps": r["steps"], "wall_s": round(time.perf_counter() - t0, 1),
                          "St_fit": round(-3.3265 / re + 0.1816 + 1.6e-4 * re, 4),
@@ -228,6 +236,116 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
                         f"r 0.5..20, u_inf 0.1, FP64; steady cases to residual {tol:g}, unsteady cases "
                         f"1500 time units of transient (transverse kick 0.2 u_inf in the near wake) then 500 sampled",
             "steady": rows, "unsteady": unsteady}
+
+
+def _shear_wave_error(sdugks, meshgen, n, nu, scheme, cfl=0.5, amp=0.01, decay=0.5):
+    """Decaying shear wave u = amp sin(2 pi y) e^(-nu k^2 t) on n x n
+    periodic quads, run from its equilibrium state until the amplitude has
+    fallen by e^-decay: relative L2 error of u at the centroids."""
+    import numpy as np
+    from paper_2007_07347_amd import cylinder
+    mesh, bcs = meshgen.periodic_box(n, n)
+    g = sdugks.geometry(mesh, bcs, nu=nu, cfl=cfl)
+    k = 2.0 * math.pi
+    steps = max(1, round(decay / (nu * k * k) / g["dt"]))
+    u0 = amp * np.sin(k * g["cy"])
+    one = np.ones(len(u0))
+    s = sdugks.Solver(mesh, bcs, nu=nu, cfl=cfl, scheme=scheme)
+    s.set_state(cylinder.equilibrium(one, u0, 0 * u0), np.c_[one, u0, 0 * u0])
+    s.step(steps)
+    _, u, v = s.macros()
+    ratio = s.dt / s.tau
+    s.close()
+    exact = u0 * math.exp(-nu * k * k * steps * g["dt"])
+    return float(np.sqrt(((u - exact) ** 2).sum() / (exact ** 2).sum())), steps, ratio
+
+
+def _stays_bounded(sdugks, mesh, bcs, state, uref, ratio, cfl, dt1, scheme, steps=20000, extra=None):
+    """True if the run keeps finite macros with speed <= 3 uref and density in
+    [0.5, 2] over the given number of steps (checked every 2000)."""
+    import numpy as np
+    s = sdugks.Solver(mesh, bcs, tau=cfl * dt1 / ratio, cfl=cfl, scheme=scheme, **(extra or {}))
+    if state is not None:
+        s.set_state(*state)
+    ok, n = True, 0
+    while ok and n < steps:
+        s.step(2000)
+        n += 2000
+        rho, u, v = s.macros()
+        sp = np.sqrt(u * u + v * v)
+        ok = bool(np.isfinite(rho).all() and np.isfinite(sp).all() and sp.max() <= 3 * uref
+                  and rho.min() >= 0.5 and rho.max() <= 2.0)
+    s.close()
+    return ok
+
+
+def original_scheme_form(sdugks, meshgen, sched, steps=3000):
+    """The original half-step DUGKS against the paper's simplified scheme,
+    both in the same fused kernel: cost per step on the headline cavity (same
+    tile schedule), accuracy on the decaying shear wave at two Dt/tau, and the
+    largest CFL that stays bounded for 20,000 steps as a function of Dt/tau,
+    on a cavity with walls and on periodic triangles."""
+    import numpy as np
+    import torch
+    from paper_2007_07347_amd import cylinder
+    cost = {}
+    mesh, bcs = meshgen.cavity(256, beta=1.5, U=0.1)
+    for prec, pname in ((sdugks.FP64, "f64"), (sdugks.FP32DEV, "fp32dev")):
+        for scheme, sname in ((sdugks.SCHEME_SIMPLIFIED, "simplified"), (sdugks.SCHEME_ORIGINAL, "original")):
+            s = sdugks.Solver(mesh, bcs, nu=1e-4, cfl=0.5, precision=prec, scheme=scheme, **sched)
+            s.step(300)
+            torch.cuda.synchronize()
+            ms = time_steps(s.step, steps)
+            cost[f"{sname}_{pname}_mlups"] = round(s.n_cells * steps / (ms / 1e3) / 1e6, 1)
+            s.close()
+    accuracy = []
+    for nu in (1e-2, 1e-3, 1e-4):
+        for n in (32, 64, 128):
+            row = {"n": n, "nu": nu}
+            for scheme, sname in ((sdugks.SCHEME_SIMPLIFIED, "simplified"), (sdugks.SCHEME_ORIGINAL, "original")):
+                err, nst, ratio = _shear_wave_error(sdugks, meshgen, n, nu, scheme)
+                row[f"{sname}_err"] = float(f"{err:.4g}")
+            row.update(steps=nst, dt_over_tau=round(ratio, 4))
+            accuracy.append(row)
+    ratios = (0.01, 0.03, 0.1, 0.3, 1.0, 10.0, 100.0)
+
+    def tri_state():
+        m, b = meshgen.jittered_periodic_triangles(32, seed=1)
+        g = sdugks.geometry(m, b, nu=0.01)
+        u = 0.05 * np.sin(2 * math.pi * g["cy"])
+        one = np.ones(len(u))
+        return m, b, (cylinder.equilibrium(one, u, 0 * u), np.c_[one, u, 0 * u]), 0.05
+
+    cases = {"cavity 64x64 tanh(1.5), walls, from rest": meshgen.cavity(64) + (None, 0.1),
+             "periodic jittered triangles 32x32x2, shear wave": tri_state()}
+    stability = []
+    for cname, (m, b, state, uref) in cases.items():
+        dt1 = sdugks.geometry(m, b, nu=0.01, cfl=1.0)["dt"]
+        for scheme, sname in ((sdugks.SCHEME_SIMPLIFIED, "simplified"), (sdugks.SCHEME_ORIGINAL, "original")):
+            row = {"case": cname, "scheme": sname, "max_cfl": []}
+            for ratio in ratios:
+                ok = lambda c: _stays_bounded(sdugks, m, b, state, uref, ratio, c, dt1, scheme)
+                lo, hi = 0.25, 2.5
+                if not ok(lo):
+                    row["max_cfl"].append(f"<{lo}")
+                    continue
+                if ok(hi):
+                    row["max_cfl"].append(f">={hi}")
+                    continue
+                for _ in range(5):
+                    mid = 0.5 * (lo + hi)
+                    lo, hi = (mid, hi) if ok(mid) else (lo, mid)
+                row["max_cfl"].append(round(lo, 3))
+            progress(f"stability {cname} {sname}: {row['max_cfl']}")
+            stability.append(row)
+    return {"cost": {"workload": "lid-driven cavity 256x256 tanh(1.5), Re 1000, CFL 0.5, headline tile schedule",
+                     "steps": steps, **cost},
+            "shear_wave_accuracy": {"workload": "periodic n x n quads, u = 0.01 sin(2 pi y), CFL 0.5, "
+                                                "run until the amplitude has decayed by e^-0.5",
+                                    "rows": accuracy},
+            "stability": {"criterion": "finite, speed <= 3 u_ref, density in [0.5, 2] over 20000 steps; "
+                                       "largest CFL by bisection in [0.25, 2.5]",
+                          "dt_over_tau": list(ratios), "rows": stability}}
 
 
 def cpu_baseline(mesh, bcs, kw, target_s):
@@ -261,6 +379,7 @@ def main():
 
     s, mesh, bcs, kw, sched, nc, ms, wall, eps, kt = headline(sdugks, autotune, meshgen, a, sdugks.FP64)
     mlups = nc * a.steps / (ms / 1e3) / 1e6
+    progress(f"headline {mlups:.1f} MLUPS")
     kname = max(kt, key=kt.get)
     # one launch of the step kernel per step: its average duration is the timed
     # region (HIP events on the solver's stream) over the step count (the six
@@ -295,9 +414,13 @@ def main():
                           "alg_bytes_per_cell": ALG_BYTES["fp32dev"],
                           "traffic": measured_traffic("cavity256_fp32dev")}
         s32.close()
+        progress("fp32 deviation form done")
         out["batch"] = batch_form(sdugks, autotune, meshgen)
+        progress("batched form done")
         out["serving"] = serving(meshgen)
+        progress("serving trace done")
         out["cylinder"] = cylinder_form(meshgen)
+        out["original_scheme"] = original_scheme_form(sdugks, meshgen, sched)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, bcs, kw, a.cpu_seconds)
     print(json.dumps(out), flush=True)
