@@ -41,7 +41,7 @@ struct Layout {
     size_t off_f[2]{}, off_W[2]{}, off_G[2]{}, off_fbp = 0, off_sg = 0, off_snap = 0;
     size_t off_nbr = 0, off_geo = 0, off_ainv = 0, off_dtv = 0, off_area = 0, off_bft = 0, off_bcs = 0;
     size_t off_part = 0, off_out = 0, total = 0;
-    size_t off_thdr = 0, off_lgid = 0, off_ladj = 0, off_lw = 0;
+    size_t off_thdr = 0, off_lgid = 0, off_ladj = 0, off_lfc = 0, off_frec = 0, off_lw = 0;
     size_t off_bq_hdr = 0, off_bq_nb = 0, off_bq_w = 0, off_bq_geo = 0, off_bq_out = 0, off_bq_sum = 0;
 };
 
@@ -67,6 +67,8 @@ Layout make_layout(const MeshBuild &mb, int precision)
         L.off_thdr = take(mb.tile_hdr.size() * sizeof(int32_t));
         L.off_lgid = take(mb.lgid.size() * sizeof(int32_t));
         L.off_ladj = take(mb.ladj.size() * sizeof(int16_t));
+        L.off_lfc = take(mb.lfc.size() * sizeof(int16_t));
+        L.off_frec = take(mb.frec.size() * (dev ? sizeof(float) : sizeof(double)));
         L.off_lw = take(mb.lw.size() * (dev ? sizeof(float) : sizeof(double)));
     } else {
         L.off_fbp = take(9 * row);
@@ -76,7 +78,7 @@ Layout make_layout(const MeshBuild &mb, int precision)
         L.off_bft = take(std::max<size_t>(1, mb.n_bfaces) * sizeof(int32_t));
     }
     L.off_snap = take(2 * row);
-    L.off_geo = take(6 * (size_t)mb.D * rowf);
+    if (mb.n_tiles == 0) L.off_geo = take(6 * (size_t)mb.D * rowf);
     L.off_dtv = take(row);
     L.off_area = take(row);
     L.off_bcs = take(std::max<size_t>(1, mb.bcs.size()) * sizeof(DevBC));
@@ -339,7 +341,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     };
     // geometry
     const bool dev = h->dev32(), tiled = mb.n_tiles > 0;
-    {
+    if (!tiled) {
         // face geometry as (x, y) pairs: rows [3][D] (l n, r_self, r_other) of np pairs each
         const size_t D = mb.D, n_geo = 3 * D * np * 2;
         std::vector<double> geo(n_geo, 0.0);
@@ -422,27 +424,37 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         auto up = [&](size_t off, const void *src, size_t bytes) {
             return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
         };
-        std::vector<float> lw32;
-        if (dev) lw32.assign(mb.lw.begin(), mb.lw.end());
+        std::vector<float> frec32, lw32;
+        if (dev) { frec32.assign(mb.frec.begin(), mb.frec.end()); lw32.assign(mb.lw.begin(), mb.lw.end()); }
         if (!up(L.off_thdr, mb.tile_hdr.data(), mb.tile_hdr.size() * sizeof(int32_t)) ||
             !up(L.off_lgid, mb.lgid.data(), mb.lgid.size() * sizeof(int32_t)) ||
             !up(L.off_ladj, mb.ladj.data(), mb.ladj.size() * sizeof(int16_t)) ||
+            !up(L.off_lfc, mb.lfc.data(), mb.lfc.size() * sizeof(int16_t)) ||
+            !(dev ? up(L.off_frec, frec32.data(), frec32.size() * sizeof(float))
+                  : up(L.off_frec, mb.frec.data(), mb.frec.size() * sizeof(double))) ||
             !(dev ? up(L.off_lw, lw32.data(), lw32.size() * sizeof(float))
                   : up(L.off_lw, mb.lw.data(), mb.lw.size() * sizeof(double))))
             return cleanup(fail(SDUGKS_EHIP, "upload of the tile tables failed"));
         h->dt.n_tiles = mb.n_tiles;
         h->dt.nl_max = mb.nl_max;
         h->dt.na_max = mb.na_max;
+        h->dt.nt_max = mb.nt_max;
+        h->dt.nf_max = std::max<int32_t>(1, mb.nf_max);
         h->dt.hdr = h->at<int32_t>(L.off_thdr);
         h->dt.lgid = h->at<int32_t>(L.off_lgid);
         h->dt.ladj = h->at<int16_t>(L.off_ladj);
+        h->dt.lfc = h->at<int16_t>(L.off_lfc);
+        h->dt.fr = dev ? nullptr : h->at<double2>(L.off_frec);
+        h->dt.fr32 = dev ? h->at<float2>(L.off_frec) : nullptr;
         h->dt.lw = dev ? nullptr : h->at<double2>(L.off_lw);
         h->dt.lw32 = dev ? h->at<float2>(L.off_lw) : nullptr;
     }
     DevMesh &d = h->dm;
     d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces; d.n_bc = (int32_t)mb.bcs.size();
     const size_t blk = (size_t)mb.D * np;
-    if (dev) {
+    if (tiled) {
+        // the fused step reads its face records instead
+    } else if (dev) {
         const float2 *g = h->at<float2>(L.off_geo);
         d.ln32 = g; d.rs32 = g + blk; d.ro32 = g + 2 * blk;
     } else {

@@ -32,7 +32,8 @@ struct DevMesh {
     // scheme, (dt/2, dt/4tau, 2tau/(2tau+dt/2)) for the original one
     double dtr, fb, fc1;
     int32_t scheme;                     // 0 the paper's scheme, 1 the original one
-    // FP32 copies of the face geometry for the deviation form (null otherwise)
+    // FP32 copies of the face geometry for the deviation form (null otherwise;
+    // the per-slot face geometry is only kept for the two-kernel step)
     const float2 *ln32, *rs32, *ro32;
     double rho0;                        // offset of the deviation form: f = w_i rho0 + stored value
 };
@@ -47,15 +48,18 @@ struct DevState {
 };
 
 // Tiles of the fused step (see MeshBuild): headers [n_tiles][8] (g0, nt, n1,
-// n2), and the padded per-tile tables lgid [PL], ladj [D][PA], lw [D][PA]
-// (x, y pairs) with PL = nl_max, PA = na_max.
+// n2), the padded per-tile tables lgid [PL], ladj [D][PA], lfc [D][PT] and the
+// face records [3][PF] (rows l n, r_self, r_other of (x, y) pairs) and the
+// least-squares weights lw [D][PA] ((x, y) pairs), with PL = nl_max,
+// PA = na_max, PT = nt_max, PF = nf_max.
 struct DevTiles {
-    int32_t n_tiles, nl_max, na_max;
+    int32_t n_tiles, nl_max, na_max, nt_max, nf_max;
     const int32_t *hdr;
     const int32_t *lgid;
     const int16_t *ladj;
-    const double2 *lw;                  // FP64 form
-    const float2 *lw32;                 // deviation form
+    const int16_t *lfc;
+    const double2 *fr, *lw;             // FP64 form
+    const float2 *fr32, *lw32;          // deviation form
 };
 
 // One member of a batched launch: its mesh, tiles, both ping-pong buffers

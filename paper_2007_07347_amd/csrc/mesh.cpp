@@ -114,8 +114,9 @@ void rcb(std::vector<int32_t> &ids, size_t lo, size_t hi, int64_t k, const std::
 
 // Tiles of the fused step over the internal order (tile-major already).
 // Every per-tile table is padded to the largest tile so tile t's block starts
-// at t times a fixed pitch.
-void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &parts)
+// at t times a fixed pitch.  False if the two views of some face are not exact
+// mirrors (they always are: both are built from one face record below).
+bool build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &parts)
 {
     const int32_t nc = out.nc, D = out.D;
     out.n_tiles = (int32_t)parts.size();
@@ -175,6 +176,55 @@ void build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &p
         }
         for (int32_t c : L) loc[c] = -1;
     }
+    // pass 3: one face record per face of the tile cells, and each slot's code
+    int32_t n_face_ids = 0;
+    for (int32_t f : out.fid) n_face_ids = std::max(n_face_ids, f + 1);
+    std::vector<int32_t> rec_of(n_face_ids, -1);
+    std::vector<std::vector<double>> recs(out.n_tiles);
+    std::vector<std::vector<int16_t>> codes(out.n_tiles);
+    out.nt_max = out.nf_max = 0;
+    for (int32_t t = 0; t < out.n_tiles; t++) out.nt_max = std::max(out.nt_max, out.tile_hdr[(size_t)t * 8 + 1]);
+    const size_t PT = out.nt_max;
+    for (int32_t t = 0; t < out.n_tiles; t++) {
+        const int32_t g0 = out.tile_hdr[(size_t)t * 8], nt = out.tile_hdr[(size_t)t * 8 + 1];
+        std::vector<double> &R = recs[t];
+        codes[t].assign((size_t)D * PT, -1);
+        std::vector<int32_t> used;
+        for (int32_t k = 0; k < nt; k++)
+            for (int32_t s = 0; s < D; s++) {
+                const size_t q = (size_t)s * nc + g0 + k;
+                const int32_t f = out.fid[q];
+                if (f < 0) continue;
+                const double v[6] = {out.lnx[q], out.lny[q], out.rsx[q], out.rsy[q], out.rox[q], out.roy[q]};
+                int32_t code;
+                if (rec_of[f] < 0) {
+                    rec_of[f] = (int32_t)(R.size() / 6);
+                    used.push_back(f);
+                    R.insert(R.end(), v, v + 6);
+                    code = 2 * rec_of[f];
+                } else {
+                    const double *r = &R[(size_t)rec_of[f] * 6];
+                    if (!(v[0] == -r[0] && v[1] == -r[1] && v[2] == r[4] && v[3] == r[5] && v[4] == r[2] && v[5] == r[3]))
+                        return false;
+                    code = 2 * rec_of[f] + 1;
+                }
+                codes[t][(size_t)s * PT + k] = (int16_t)code;
+            }
+        for (int32_t f : used) rec_of[f] = -1;
+        out.nf_max = std::max(out.nf_max, (int32_t)(R.size() / 6));
+    }
+    const size_t PF = std::max<int32_t>(1, out.nf_max);
+    out.lfc.assign((size_t)out.n_tiles * D * PT, -1);
+    out.frec.assign((size_t)out.n_tiles * 3 * PF * 2, 0.0);
+    for (int32_t t = 0; t < out.n_tiles; t++) {
+        std::copy(codes[t].begin(), codes[t].end(), out.lfc.begin() + (size_t)t * D * PT);
+        const std::vector<double> &R = recs[t];
+        for (size_t r = 0; r < R.size() / 6; r++)
+            for (size_t k = 0; k < 3; k++)
+                for (size_t e = 0; e < 2; e++)
+                    out.frec[(((size_t)t * 3 + k) * PF + r) * 2 + e] = R[r * 6 + 2 * k + e];
+    }
+    return true;
 }
 
 }  // namespace
@@ -394,6 +444,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     out.lnx.assign(ns, 0); out.lny.assign(ns, 0); out.rsx.assign(ns, 0); out.rsy.assign(ns, 0);
     out.rox.assign(ns, 0); out.roy.assign(ns, 0);
     out.wx.assign(ns, 0); out.wy.assign(ns, 0);
+    out.fid.assign(ns, -1);
     out.bf_cell.clear(); out.bf_tag.clear();
     std::vector<int32_t> bf_index(faces.size(), -1);
     for (size_t fi = 0; fi < faces.size(); fi++)
@@ -413,6 +464,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
         for (int32_t s = 0; s < deg; s++) {
             const Face &f = faces[slot_face[(size_t)c * D + s]];
             size_t q = (size_t)s * nc + k;
+            out.fid[q] = slot_face[(size_t)c * D + s];
             bool own = (f.o == c && f.os == s);
             // face data from the owner's side: midpoint, its image on the neighbour side
             double ro_x = f.xm - cx[f.o], ro_y = f.ym - cy[f.o];
@@ -465,9 +517,9 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
         if (bc[t].type == SDUGKS_BC_SYMMETRY) { out.bcs[t].u = sym_nx[t]; out.bcs[t].v = sym_ny[t]; }   // the line's normal
     }
     out.tile_T = 0; out.n_tiles = 0;
-    out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lw.clear();
+    out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lfc.clear(); out.frec.clear(); out.lw.clear();
     if (tiled) {
-        build_tiles(out, parts);
+        if (!build_tiles(out, parts)) BAD("internal: the two views of a face are not exact mirrors");
         if (tile_lds_bytes(out.nl_max, out.na_max, n_bc) > kTileLdsLimit || out.nl_max > B) {
             // one thread per local cell and LDS for all of them: bisect into smaller tiles
             if (T <= 4) BAD("mesh too irregular for the fused step's tiles");

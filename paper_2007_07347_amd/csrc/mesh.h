@@ -37,6 +37,7 @@ struct MeshBuild {
     std::vector<double> rsx, rsy; // face midpoint minus this cell's centroid
     std::vector<double> rox, roy; // face midpoint (in the neighbour's frame) minus the neighbour's centroid
     std::vector<double> wx, wy;   // least-squares weight A^-1 d of the stencil point behind the slot
+    std::vector<int32_t> fid;     // face behind the slot (both cells of an interior face share it); -1 empty
     // boundary faces
     std::vector<int32_t> bf_cell, bf_tag;
     std::vector<BcEntry> bcs;
@@ -44,16 +45,29 @@ struct MeshBuild {
     // owns the contiguous internal cells [g0, g0 + nt); its local cells are
     // those, then the n1 cells of its first halo ring, then the n2 of its
     // second.  Per-tile tables, padded to the largest tile (PL = nl_max local
-    // cells, PA = na_max cells of tile + first ring):
+    // cells, PA = na_max cells of tile + first ring, PT = nt_max tile cells,
+    // PF = nf_max face records):
     //   lgid [n_tiles][PL]          internal id of every local cell;
     //   ladj [n_tiles][D][PA]       neighbour behind each slot of a tile or
     //                               first-ring cell: local index >= 0, -1 empty,
     //                               -2 - tag for a boundary face of that tag;
-    //   lw   [n_tiles][D][PA][2]    its least-squares weight (x, y).
-    int32_t tile_T = 0, n_tiles = 0, nl_max = 0, na_max = 0;
+    //   lfc  [n_tiles][D][PT]       face of each slot of a tile cell: record
+    //                               index * 2, + 1 if the record is stored as
+    //                               seen from the other cell; -1 empty;
+    //   frec [n_tiles][3][PF][2]    one record per face of the tile's cells, as
+    //                               seen from the first tile cell that has it:
+    //                               rows l n, r_self, r_other of (x, y).  A face
+    //                               between two tile cells is stored once; the
+    //                               other cell's view is (-l n, r_other, r_self),
+    //                               the exact mirror the per-slot arrays hold.
+    //   lw   [n_tiles][D][PA][2]    least-squares weight (x, y) behind each slot
+    //                               of a tile or first-ring cell.
+    int32_t tile_T = 0, n_tiles = 0, nl_max = 0, na_max = 0, nt_max = 0, nf_max = 0;
     std::vector<int32_t> tile_hdr;   // [n_tiles][8]: g0, nt, n1, n2, 0...
     std::vector<int32_t> lgid;
     std::vector<int16_t> ladj;
+    std::vector<int16_t> lfc;
+    std::vector<double> frec;
     std::vector<double> lw;
 };
 

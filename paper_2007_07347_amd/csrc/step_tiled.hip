@@ -22,9 +22,11 @@
 // compensated (TwoSum), and W, its update, feq and the macroscopic fluxes in
 // FP64.
 //
-// Every global input of phases 2 and 3 (weights, adjacency, face geometry,
-// the old f of the lane's velocities) is requested at kernel start, so its
-// latency overlaps phase 1.  Each XCD sweeps a contiguous range of bisection
+// Every global input of phases 2 and 3 (adjacency, least-squares weights,
+// face records) is requested at kernel start, so its latency overlaps phase 1.
+// The faces of a tile's cells are one table of records per tile: a face
+// between two tile cells is read once and used by both cells, mirrored.  Each
+// XCD sweeps a contiguous range of bisection
 // tiles, so the halo cells a tile reads are mostly L2 hits.  A face shared by
 // two tiles is evaluated by both from identical operands: the flux that
 // leaves one cell enters the other exactly.
@@ -171,25 +173,33 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // boundary-condition table [n_bc][4]: type, rho, u, v (16-byte aligned after the gradient)
     double *sbc = smem + ((5 * P * 8 + (9 * P + 18 * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
+    const int16_t *lfc = tl.lfc + (size_t)t * D * tl.nt_max;
     using R2 = typename std::conditional<DEV, float2, double2>::type;
-    const R2 *lw, *gln, *grs, *gro;
+    const R2 *lw, *frt;
     if constexpr (DEV) {
         lw = tl.lw32 + (size_t)t * D * P1;
-        gln = m.ln32; grs = m.rs32; gro = m.ro32;
+        frt = tl.fr32 + (size_t)t * tl.nf_max * 3;
     } else {
         lw = tl.lw + (size_t)t * D * P1;
-        gln = m.ln; grs = m.rs; gro = m.ro;
+        frt = tl.fr + (size_t)t * tl.nf_max * 3;
     }
+    const int PF = tl.nf_max;
     // fbar+ from the cell variable (phase 1); the face step: reconstruction
     // time and the coefficients of the face distribution (phase 3)
     const R ra = (R)m.a, rb_ = (R)m.b, rc1 = (R)m.fc1, rbf = (R)m.fb, rdt = (R)m.dtr;
-    // ---- requests of all phases, in this order: the local cell ids; the
-    // inputs of phases 2 and 3 (adjacency, weights, face geometry, boundary
-    // table), which need nothing loaded first; then the phase-1 state at the
-    // cell ids.  Loads are unconditional at clamped (valid) indices, lanes
-    // without work ignore what they read (padded cell ids are 0, a valid cell).
+    // ---- requests of all phases, in this order: the local cell ids and the
+    // face codes of the lanes; the adjacency, least-squares weights and
+    // boundary table, which need nothing loaded first; the phase-1 state at
+    // the cell ids; then the face records at the face codes.  Loads are
+    // unconditional at clamped (valid) indices, lanes without work ignore
+    // what they read (padded cell ids are 0, a valid cell; empty slots read
+    // record 0).
     const bool p1 = tid < nl;
     const unsigned g1 = (unsigned)tl.lgid[(size_t)t * P + (p1 ? tid : 0)];
+    const int lc3 = tid >> 2, sl3 = tid & 3;
+    const bool p3 = lc3 < nt;
+    const int sl3c = sl3 < D ? sl3 : D - 1;
+    const int fc3 = lfc[sl3c * tl.nt_max + (p3 ? lc3 : 0)];
     __builtin_amdgcn_sched_barrier(0);
     const bool p2 = tid < na;
     const int t2 = p2 ? tid : 0;
@@ -203,15 +213,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         wx2[sl] = w.x;
         wy2[sl] = w.y;
     }
-    const int lc3 = tid >> 2, sl3 = tid & 3;
-    const bool p3 = lc3 < nt;
     const int g3 = g0 + (p3 ? lc3 : 0);
-    const int sl3c = sl3 < D ? sl3 : D - 1;
     const int a3 = ladj[sl3c * P1 + (p3 ? lc3 : 0)];
     const int la3 = (p3 && sl3 < D) ? a3 : -1;
-    const int q3 = sl3c * np + g3;
-    const R2 lnv = gln[q3], rsv = grs[q3], rov = gro[q3];
-    const R lnx = lnv.x, lny = lnv.y, rsx = rsv.x, rsy = rsv.y, rox = rov.x, roy = rov.y;
     const bool pb = tid < m.n_bc;
     const DevBC bcl = m.bcs[pb ? tid : 0];
     __builtin_amdgcn_sched_barrier(0);
@@ -222,6 +226,15 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         if constexpr (DEV) fv[i] = s.f32[(size_t)i * np + g1];
         else fv[i] = s.f[(size_t)i * np + g1];
     }
+    __builtin_amdgcn_sched_barrier(0);
+    // the lane's face: the record as seen from the lane's cell (l n, r_self,
+    // r_other), or from the other cell (-l n, r_other, r_self)
+    const int rec = fc3 >= 0 ? fc3 >> 1 : 0;
+    const R2 lnv = frt[rec], rav = frt[PF + rec], rbv = frt[2 * PF + rec];
+    const bool flip = (fc3 & 1) != 0;
+    const R lnx = flip ? -lnv.x : lnv.x, lny = flip ? -lnv.y : lnv.y;
+    const R rsx = flip ? rbv.x : rav.x, rsy = flip ? rbv.y : rav.y;
+    const R rox = flip ? rav.x : rbv.x, roy = flip ? rav.y : rbv.y;
 
     // ---- phase 1: macros and fbar+ of every local cell
     if (pb) {
