@@ -124,6 +124,5 @@ hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBn
 hipError_t launch_poke_nan(void *p, int bytes, hipStream_t st);
 
 constexpr int kReduceBlocks = 256;
-constexpr int kXcds = 8;           // accelerator complex dies of an MI355X, each with its own L2
 
 }  // namespace sdg

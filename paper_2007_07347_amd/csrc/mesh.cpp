@@ -116,10 +116,26 @@ void rcb(std::vector<int32_t> &ids, size_t lo, size_t hi, int64_t k, const std::
 // Every per-tile table is padded to the largest tile so tile t's block starts
 // at t times a fixed pitch.  False if the two views of some face are not exact
 // mirrors (they always are: both are built from one face record below).
-bool build_tiles(MeshBuild &out, const std::vector<std::pair<size_t, size_t>> &parts)
+bool build_tiles(MeshBuild &out, std::vector<std::pair<size_t, size_t>> parts)
 {
     const int32_t nc = out.nc, D = out.D;
     out.n_tiles = (int32_t)parts.size();
+    // Tiles with a boundary face do more work (boundary states in phases 2 and
+    // 3).  Each XCD takes a contiguous range of tiles and starts them in order,
+    // so within each range those tiles go first.
+    {
+        const size_t per = (parts.size() + kXcds - 1) / kXcds;
+        auto at_boundary = [&](const std::pair<size_t, size_t> &p) {
+            for (size_t c = p.first; c < p.second; c++)
+                for (int32_t s = 0; s < D; s++) {
+                    const int32_t nb = out.nbr[(size_t)s * nc + c];
+                    if (nb < 0 && nb != kEmptySlot) return true;
+                }
+            return false;
+        };
+        for (size_t lo = 0; lo < parts.size(); lo += per)
+            std::stable_partition(parts.begin() + lo, parts.begin() + std::min(lo + per, parts.size()), at_boundary);
+    }
     out.tile_hdr.assign((size_t)out.n_tiles * 8, 0);
     std::vector<std::vector<int32_t>> locals(out.n_tiles);
     std::vector<int32_t> stamp(nc, -1), h1, h2;

@@ -71,6 +71,9 @@ struct MeshBuild {
     std::vector<double> lw;
 };
 
+// Accelerator complex dies of an MI355X, each with its own L2: the fused step
+// gives each a contiguous range of tiles.
+constexpr int32_t kXcds = 8;
 // Boundary-condition entries the fused step keeps in LDS (more: two-kernel step).
 constexpr int32_t kMaxTileBcs = 64;
 // LDS bytes of one workgroup of the fused step: per local cell W, u and fbar+,
