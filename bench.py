@@ -58,9 +58,19 @@ def parse():
     return p.parse_args()
 
 
+def code_hash(text):
+    """sha1 (16 hex digits) of a C++ source with comments, blank lines and
+    trailing blanks removed: edits to comments leave the compiled kernel, and
+    so this hash, unchanged."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.splitlines()]
+    return hashlib.sha1("\n".join(ln for ln in lines if ln).encode()).hexdigest()[:16]
+
+
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha1(fh.read()).hexdigest()[:16]
+    with open(KERNEL_SRC) as fh:
+        return code_hash(fh.read())
 
 
 def measured_traffic(workload):
@@ -72,7 +82,7 @@ def measured_traffic(workload):
     except (OSError, ValueError):
         return None
     e = t.get(workload)
-    if not e or e.get("kernel_sha1") != kernel_hash():
+    if not e or e.get("kernel_code_sha1") != kernel_hash():
         return None
     return e.get("bytes_per_launch")
 

@@ -46,9 +46,10 @@ struct Layout {
 };
 
 // What the three step forms need: the two-kernel step keeps fbar+ and its
-// gradient in memory with per-cell neighbour lists and inverse normal
-// matrices; the fused step keeps its tile tables instead; the deviation form
-// stores f and the face geometry in FP32.
+// gradient in memory with per-cell neighbour lists, inverse normal matrices
+// and per-slot face geometry; the fused step keeps its tile tables (with the
+// face records) instead; the deviation form stores f, the face records and
+// the least-squares weights in FP32.
 Layout make_layout(const MeshBuild &mb, int precision)
 {
     Layout L;
@@ -78,7 +79,7 @@ Layout make_layout(const MeshBuild &mb, int precision)
         L.off_bft = take(std::max<size_t>(1, mb.n_bfaces) * sizeof(int32_t));
     }
     L.off_snap = take(2 * row);
-    if (mb.n_tiles == 0) L.off_geo = take(6 * (size_t)mb.D * rowf);
+    if (mb.n_tiles == 0) L.off_geo = take(6 * (size_t)mb.D * row);   // two-kernel step: FP64 only
     L.off_dtv = take(row);
     L.off_area = take(row);
     L.off_bcs = take(std::max<size_t>(1, mb.bcs.size()) * sizeof(DevBC));
@@ -342,7 +343,8 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     // geometry
     const bool dev = h->dev32(), tiled = mb.n_tiles > 0;
     if (!tiled) {
-        // face geometry as (x, y) pairs: rows [3][D] (l n, r_self, r_other) of np pairs each
+        // two-kernel step (FP64 only): face geometry as (x, y) pairs, rows [3][D]
+        // (l n, r_self, r_other) of np pairs each
         const size_t D = mb.D, n_geo = 3 * D * np * 2;
         std::vector<double> geo(n_geo, 0.0);
         const std::vector<double> *parts[3][2] = {{&mb.lnx, &mb.lny}, {&mb.rsx, &mb.rsy}, {&mb.rox, &mb.roy}};
@@ -351,14 +353,8 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
                 for (size_t c = 0; c < nc; c++)
                     for (size_t e = 0; e < 2; e++)
                         geo[((k * D + sl) * np + c) * 2 + e] = (*parts[k][e])[sl * nc + c];
-        hipError_t e;
-        if (dev) {
-            std::vector<float> g32(geo.begin(), geo.end());
-            e = hipMemcpy(h->at<float>(L.off_geo), g32.data(), n_geo * sizeof(float), hipMemcpyHostToDevice);
-        } else {
-            e = hipMemcpy(h->at<double>(L.off_geo), geo.data(), n_geo * sizeof(double), hipMemcpyHostToDevice);
-        }
-        if (e != hipSuccess) return cleanup(fail(SDUGKS_EHIP, "upload of the face geometry failed"));
+        if (hipMemcpy(h->at<double>(L.off_geo), geo.data(), n_geo * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(SDUGKS_EHIP, "upload of the face geometry failed"));
     }
     if (!tiled) {
         rc = upload_rows(h->at<int32_t>(L.off_nbr), mb.nbr, mb.D, nc, np, h->stream);
@@ -452,12 +448,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     DevMesh &d = h->dm;
     d.nc = mb.nc; d.np = (int32_t)np; d.D = mb.D; d.n_bfaces = mb.n_bfaces; d.n_bc = (int32_t)mb.bcs.size();
     const size_t blk = (size_t)mb.D * np;
-    if (tiled) {
-        // the fused step reads its face records instead
-    } else if (dev) {
-        const float2 *g = h->at<float2>(L.off_geo);
-        d.ln32 = g; d.rs32 = g + blk; d.ro32 = g + 2 * blk;
-    } else {
+    if (!tiled) {
         const double2 *g = h->at<double2>(L.off_geo);
         d.ln = g; d.rs = g + blk; d.ro = g + 2 * blk;
     }

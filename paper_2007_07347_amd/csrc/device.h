@@ -17,6 +17,7 @@ struct DevBC {
 struct DevMesh {
     int32_t nc, np, D, n_bfaces, n_bc;
     const int32_t *nbr;                 // [D][np]
+    // two-kernel step only (the fused step reads per-tile face records):
     const double2 *ln;                  // [D][np] scaled outward normal (x, y)
     const double2 *rs;                  // [D][np] midpoint - own centroid
     const double2 *ro;                  // [D][np] midpoint image - neighbour centroid
@@ -32,9 +33,6 @@ struct DevMesh {
     // scheme, (dt/2, dt/4tau, 2tau/(2tau+dt/2)) for the original one
     double dtr, fb, fc1;
     int32_t scheme;                     // 0 the paper's scheme, 1 the original one
-    // FP32 copies of the face geometry for the deviation form (null otherwise;
-    // the per-slot face geometry is only kept for the two-kernel step)
-    const float2 *ln32, *rs32, *ro32;
     double rho0;                        // offset of the deviation form: f = w_i rho0 + stored value
 };
 

@@ -16,7 +16,7 @@
 //            f^{n+1} (Eq. fn+1), each lane writing two or three velocities.
 //
 // Two storage forms share the code: FP64 f, or (DEV) the deviation
-// f - w_i rho0 in FP32 with FP32 face geometry, gradients and face fluxes
+// f - w_i rho0 in FP32 with FP32 face records, gradients and face fluxes
 // computed on deviations (the constant parts cancel exactly: sum_i w_i e_i = 0
 // and the scaled normals of a closed cell sum to zero), per-cell flux sums
 // compensated (TwoSum), and W, its update, feq and the macroscopic fluxes in
@@ -26,10 +26,10 @@
 // face records) is requested at kernel start, so its latency overlaps phase 1.
 // The faces of a tile's cells are one table of records per tile: a face
 // between two tile cells is read once and used by both cells, mirrored.  Each
-// XCD sweeps a contiguous range of bisection
-// tiles, so the halo cells a tile reads are mostly L2 hits.  A face shared by
-// two tiles is evaluated by both from identical operands: the flux that
-// leaves one cell enters the other exactly.
+// XCD sweeps a contiguous range of bisection tiles, those with boundary faces
+// first, so the halo cells a tile reads are mostly L2 hits and the slower
+// tiles start earliest.  A face shared by two tiles is evaluated by both from
+// identical operands: the flux that leaves one cell enters the other exactly.
 #include <type_traits>
 #include <utility>
 

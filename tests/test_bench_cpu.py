@@ -1,0 +1,40 @@
+"""Host-side pieces of bench.py: the kernel code hash that decides whether the
+committed HBM-traffic counters still describe the step kernel, and the
+refusal of more than one GPU."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_code_hash_ignores_comments_only():
+    b = _bench()
+    src = "int f(int x)\n{\n    return x + 1;   // add one\n}\n"
+    assert b.code_hash(src) == b.code_hash("// header\nint f(int x)\n{\n\n    return x + 1;\n}\n/* end */\n")
+    assert b.code_hash(src) != b.code_hash(src.replace("x + 1", "x + 2"))
+    assert b.code_hash(src) != b.code_hash(src.replace("return x", "return  x"))
+
+
+def test_traffic_record_matches_current_kernel():
+    """The committed counters carry the code hash of the kernel they were
+    taken on; bench.py reports them only while it matches."""
+    b = _bench()
+    t = b.measured_traffic("cavity256_f64")
+    if t is not None:
+        assert t > 0
+    assert b.measured_traffic("no such workload") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
