@@ -165,13 +165,14 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     const int np = m.np;
     const int tid = threadIdx.x;
     double *sW = smem;                                        // [5][P]: rho, rho u, rho v, u, v
-    // per cell: fbar+ [P][9] (deviation in DEV) and its gradient [P1][18]
-    // (x components 0..8, y components 9..17); cell-major, so the velocity
-    // and component are constant offsets of one per-cell address
+    // per cell: fbar+ [P][9] (deviation in DEV) and its gradient [P1][SG]
+    // (x components 0..8, y components 9..17, one pad); cell-major, so the
+    // velocity and component are constant offsets of one per-cell address
     R *sfbp = reinterpret_cast<R *>(smem + 5 * P);
     R *ssg = sfbp + 9 * P;
     // boundary-condition table [n_bc][4]: type, rho, u, v (16-byte aligned after the gradient)
-    double *sbc = smem + ((5 * P * 8 + (9 * P + 18 * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
+    constexpr int SG = kGradStride;
+    double *sbc = smem + ((5 * P * 8 + (9 * P + SG * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
     const int16_t *lfc = tl.lfc + (size_t)t * D * tl.nt_max;
     using R2 = typename std::conditional<DEV, float2, double2>::type;
@@ -292,8 +293,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         }
 #pragma unroll
         for (int i = 0; i < 9; i++) {
-            ssg[tid * 18 + i] = ax[i];
-            ssg[tid * 18 + 9 + i] = ay[i];
+            ssg[tid * SG + i] = ax[i];
+            ssg[tid * SG + 9 + i] = ay[i];
         }
     }
     __syncthreads();
@@ -325,10 +326,10 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             static_for<9>([&](auto I) {
                 constexpr int i = I, EX = cEx[i], EY = cEy[i];
                 const R sn = cdot<EX, EY>(lnx, lny);
-                const R rs = sfbp[lc * 9 + i] + csub<EX>(rsx, rdt) * ssg[lc * 18 + i]
-                             + csub<EY>(rsy, rdt) * ssg[lc * 18 + 9 + i];
-                const R ro = sfbp[la * 9 + i] + csub<EX>(rox, rdt) * ssg[la * 18 + i]
-                             + csub<EY>(roy, rdt) * ssg[la * 18 + 9 + i];
+                const R rs = sfbp[lc * 9 + i] + csub<EX>(rsx, rdt) * ssg[lc * SG + i]
+                             + csub<EY>(rsy, rdt) * ssg[lc * SG + 9 + i];
+                const R ro = sfbp[la * 9 + i] + csub<EX>(rox, rdt) * ssg[la * SG + i]
+                             + csub<EY>(roy, rdt) * ssg[la * SG + 9 + i];
                 const R up = sn > (R)0 ? rs : ro;
                 fbar[i] = sn == (R)0 ? (R)0.5 * (rs + ro) : up;
             });
@@ -340,7 +341,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             static_for<9>([&](auto I) {
                 constexpr int i = I, EX = cEx[i], EY = cEy[i];
                 const R sn = cdot<EX, EY>(lnx, lny);
-                const R sx = ssg[lc * 18 + i], sy = ssg[lc * 18 + 9 + i];
+                const R sx = ssg[lc * SG + i], sy = ssg[lc * SG + 9 + i];
                 const R fb = sfbp[lc * 9 + i];
                 const R inner = fb + csub<EX>(rsx, rdt) * sx + csub<EY>(rsy, rdt) * sy;
                 // incoming: the boundary state's fbar+ carried to the foot point
