@@ -436,6 +436,13 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     if (tiled) {
         for (int32_t c = 0; c < nc; c++) perm[c] = c;
         rcb(perm, 0, nc, ((int64_t)nc + T - 1) / T, cx, cy, parts);
+        // rows of cells inside each tile (by centroid y, then x): the local
+        // indices of face neighbours then differ by near-constant offsets, so
+        // a wave's LDS gathers of neighbour data spread over the banks
+        for (const auto &p : parts)
+            std::sort(perm.begin() + p.first, perm.begin() + p.second, [&](int32_t a, int32_t b) {
+                return std::make_tuple(cy[a], cx[a], a) < std::make_tuple(cy[b], cx[b], b);
+            });
     } else if (prm->reorder) {
         std::vector<int32_t> ptr(nc + 1, 0), adj;
         for (const Face &f : faces)
