@@ -153,10 +153,16 @@ bool build_tiles(MeshBuild &out, std::vector<std::pair<size_t, size_t>> parts)
                 if (nb >= 0 && stamp[nb] != t) { stamp[nb] = t; dst.push_back(nb); }
             }
         };
+        // each ring in rows (centroid y, then x), like the tile's own cells
+        auto rows = [&](std::vector<int32_t> &v) {
+            std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) {
+                return std::make_tuple(out.cy[a], out.cx[a], a) < std::make_tuple(out.cy[b], out.cx[b], b);
+            });
+        };
         for (int32_t k = 0; k < nt; k++) ring(g0 + k, h1);
-        std::sort(h1.begin(), h1.end());
+        rows(h1);
         for (int32_t c : h1) ring(c, h2);
-        std::sort(h2.begin(), h2.end());
+        rows(h2);
         std::vector<int32_t> &L = locals[t];
         for (int32_t k = 0; k < nt; k++) L.push_back(g0 + k);
         L.insert(L.end(), h1.begin(), h1.end());
