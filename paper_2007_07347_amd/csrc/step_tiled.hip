@@ -159,9 +159,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
 {
     using R = typename std::conditional<DEV, float, double>::type;   // storage / face arithmetic
     extern __shared__ double smem[];
-    const int *hd = tl.hdr + 8 * t;
-    const int g0 = hd[0], nt = hd[1], na = nt + hd[2], nl = na + hd[3];
-    const int P = tl.nl_max, P1 = tl.na_max;
+    const int P = tl.nl_max, P1 = tl.na_max, PT = tl.nt_max;
     const int np = m.np;
     const int tid = threadIdx.x;
     double *sW = smem;                                        // [5][P]: rho, rho u, rho v, u, v
@@ -174,7 +172,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     constexpr int SG = kGradStride;
     double *sbc = smem + ((5 * P * 8 + (9 * P + SG * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
-    const int16_t *lfc = tl.lfc + (size_t)t * D * tl.nt_max;
+    const int16_t *lfc = tl.lfc + (size_t)t * D * PT;
     using R2 = typename std::conditional<DEV, float2, double2>::type;
     const R2 *lw, *frt;
     if constexpr (DEV) {
@@ -191,32 +189,28 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // ---- requests of all phases, in this order: the local cell ids and the
     // face codes of the lanes; the adjacency, least-squares weights and
     // boundary table, which need nothing loaded first; the phase-1 state at
-    // the cell ids; then the face records at the face codes.  Loads are
-    // unconditional at clamped (valid) indices, lanes without work ignore
-    // what they read (padded cell ids are 0, a valid cell; empty slots read
-    // record 0).
-    const bool p1 = tid < nl;
-    const unsigned g1 = (unsigned)tl.lgid[(size_t)t * P + (p1 ? tid : 0)];
+    // the cell ids; then the face records at the face codes.  Indices are
+    // clamped with the tables' pitches, not the tile's own counts: every
+    // padded entry is a valid filler (cell 0, no neighbour, zero weight, empty
+    // face), so no request waits for the tile header, whose counts only mask
+    // what lanes without work read.
+    const unsigned g1 = (unsigned)tl.lgid[(size_t)t * P + (tid < P ? tid : 0)];
     const int lc3 = tid >> 2, sl3 = tid & 3;
-    const bool p3 = lc3 < nt;
     const int sl3c = sl3 < D ? sl3 : D - 1;
-    const int fc3 = lfc[sl3c * tl.nt_max + (p3 ? lc3 : 0)];
+    const int lc3c = lc3 < PT ? lc3 : 0;
+    const int fc3 = lfc[sl3c * PT + lc3c];
     __builtin_amdgcn_sched_barrier(0);
-    const bool p2 = tid < na;
-    const int t2 = p2 ? tid : 0;
+    const int t2 = tid < P1 ? tid : 0;
     int la2[D];
     R wx2[D], wy2[D];
 #pragma unroll
     for (int sl = 0; sl < D; sl++) {
-        const int a = ladj[sl * P1 + t2];
-        la2[sl] = p2 ? a : -1;
+        la2[sl] = ladj[sl * P1 + t2];
         const R2 w = lw[sl * P1 + t2];
         wx2[sl] = w.x;
         wy2[sl] = w.y;
     }
-    const int g3 = g0 + (p3 ? lc3 : 0);
-    const int a3 = ladj[sl3c * P1 + (p3 ? lc3 : 0)];
-    const int la3 = (p3 && sl3 < D) ? a3 : -1;
+    const int a3 = ladj[sl3c * P1 + lc3c];
     const bool pb = tid < m.n_bc;
     const DevBC bcl = m.bcs[pb ? tid : 0];
     __builtin_amdgcn_sched_barrier(0);
@@ -228,6 +222,15 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         else fv[i] = s.f[(size_t)i * np + g1];
     }
     __builtin_amdgcn_sched_barrier(0);
+    // the tile header: first cell and the counts of tile, first-ring and
+    // second-ring cells, for the masks of each phase
+    const int *hd = tl.hdr + 8 * t;
+    const int g0 = hd[0], nt = hd[1], na = nt + hd[2], nl = na + hd[3];
+    const bool p1 = tid < nl, p2 = tid < na, p3 = lc3 < nt;
+#pragma unroll
+    for (int sl = 0; sl < D; sl++) la2[sl] = p2 ? la2[sl] : -1;
+    const int g3 = g0 + (p3 ? lc3 : 0);
+    const int la3 = (p3 && sl3 < D) ? a3 : -1;
     // the lane's face: the record as seen from the lane's cell (l n, r_self,
     // r_other), or from the other cell (-l n, r_other, r_self)
     const int rec = fc3 >= 0 ? fc3 >> 1 : 0;
