@@ -137,8 +137,7 @@ struct BatchGroup {
     size_t lds = 0;
     int n_inst = 0, n_tiles = 0, cap_inst = 0, cap_tiles = 0;
     BatchInst *d_inst = nullptr;      // device table, capacity cap_inst
-    int32_t *d_begin = nullptr;       // cap_inst + 1
-    int32_t *d_count = nullptr;       // 2
+    int2 *d_tmap = nullptr;           // batch_grid(cap_tiles) slots: member, local tile
     std::vector<int> members;         // indices into the batch's member list
 };
 
@@ -763,8 +762,7 @@ void batch_release_groups(sdugks_batch_t *b)
 {
     for (auto &g : b->groups) {
         hipFree(g.d_inst);
-        hipFree(g.d_begin);
-        hipFree(g.d_count);
+        hipFree(g.d_tmap);
     }
     b->groups.clear();
 }
@@ -801,12 +799,11 @@ int batch_build(sdugks_batch_t *b)
             g.cap_tiles = (int)next_pow2(g.n_tiles);
             g.lds = std::min(g.lds + g.lds / 4, kTileLdsLimit);    // headroom for later members
             if (hipMalloc((void **)&g.d_inst, g.cap_inst * sizeof(BatchInst)) != hipSuccess ||
-                hipMalloc((void **)&g.d_begin, (g.cap_inst + 1) * sizeof(int32_t)) != hipSuccess ||
-                hipMalloc((void **)&g.d_count, 2 * sizeof(int32_t)) != hipSuccess)
+                hipMalloc((void **)&g.d_tmap, batch_grid(g.cap_tiles) * sizeof(int2)) != hipSuccess)
                 return fail(SDUGKS_ENOMEM, "hipMalloc of a batch table failed");
         }
         b->groups = want;
-        for (auto &g : want) g.d_inst = nullptr, g.d_begin = nullptr, g.d_count = nullptr;
+        for (auto &g : want) g.d_inst = nullptr, g.d_tmap = nullptr;
     } else {
         for (size_t k = 0; k < want.size(); k++) {
             b->groups[k].members = want[k].members;
@@ -819,7 +816,8 @@ int batch_build(sdugks_batch_t *b)
     for (size_t k = 0; k < b->members.size(); k++) b->cur_at_fill[k] = b->members[k]->cur;
     for (auto &g : b->groups) {
         std::vector<BatchInst> inst(g.n_inst);
-        std::vector<int32_t> begin(g.n_inst + 1, 0);
+        std::vector<int2> seq;   // live tiles in member order: member, local tile
+        seq.reserve(g.n_tiles);
         for (int k = 0; k < g.n_inst; k++) {
             sdugks_t *h = b->members[g.members[k]];
             BatchInst &e = inst[k];
@@ -832,12 +830,18 @@ int batch_build(sdugks_batch_t *b)
             }
             e.parity0 = h->cur;
             e.lagged = h->macro == SDUGKS_MACRO_LAGGED;
-            begin[k + 1] = begin[k] + h->mb.n_tiles;
+            for (int32_t t = 0; t < h->mb.n_tiles; t++) seq.push_back(make_int2(k, t));
         }
-        const int32_t count[2] = {g.n_inst, g.n_tiles};
+        // each XCD's range of tile slots gets an equal, contiguous share of the
+        // live tiles at its start; the remaining slots are empty (-1)
+        const int32_t grid = batch_grid(g.cap_tiles), per = grid / kXcds, n = (int32_t)seq.size();
+        std::vector<int2> tmap(grid, make_int2(-1, 0));
+        for (int32_t x = 0; x < kXcds; x++) {
+            const int32_t lo = (int32_t)((int64_t)n * x / kXcds), hi = (int32_t)((int64_t)n * (x + 1) / kXcds);
+            for (int32_t j = 0; j < hi - lo; j++) tmap[(size_t)x * per + j] = seq[lo + j];
+        }
         HIPCHK(hipMemcpyAsync(g.d_inst, inst.data(), inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice, b->stream));
-        HIPCHK(hipMemcpyAsync(g.d_begin, begin.data(), begin.size() * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
-        HIPCHK(hipMemcpyAsync(g.d_count, count, sizeof count, hipMemcpyHostToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(g.d_tmap, tmap.data(), tmap.size() * sizeof(int2), hipMemcpyHostToDevice, b->stream));
         HIPCHK(hipStreamSynchronize(b->stream));
     }
     return SDUGKS_OK;
@@ -846,7 +850,7 @@ int batch_build(sdugks_batch_t *b)
 int batch_launch(sdugks_batch_t *b, int parity)
 {
     for (auto &g : b->groups) {
-        BatchTable tab{g.d_inst, g.d_begin, g.d_count};
+        BatchTable tab{g.d_inst, g.d_tmap};
         HIPCHK(launch_step_batch(tab, g.D, g.dev32, parity, g.cap_tiles, g.lds, g.block, b->stream));
     }
     return SDUGKS_OK;

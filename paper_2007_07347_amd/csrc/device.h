@@ -71,12 +71,12 @@ struct BatchInst {
     int32_t parity0, lagged;
 };
 
-// Device-side batch table: count = {members, total tiles}; tile_begin has
-// members + 1 entries.
+// Device-side batch table: the members, and for every tile slot of the
+// launch grid its member and the tile's index inside that member (member -1
+// for the slots past the live tiles).
 struct BatchTable {
     const BatchInst *inst;
-    const int32_t *tile_begin;
-    const int32_t *count;
+    const int2 *tmap;
 };
 
 // Plain boundary faces for the face-flux diagnostic, in the caller's order of

@@ -74,6 +74,9 @@ struct MeshBuild {
 // Accelerator complex dies of an MI355X, each with its own L2: the fused step
 // gives each a contiguous range of tiles.
 constexpr int32_t kXcds = 8;
+// Workgroups of a batched launch with room for cap_tiles tiles (a multiple of
+// kXcds, so each XCD has the same number of tile slots).
+inline int32_t batch_grid(int32_t cap_tiles) { return (cap_tiles + kXcds - 1) / kXcds * kXcds; }
 // Boundary-condition entries the fused step keeps in LDS (more: two-kernel step).
 constexpr int32_t kMaxTileBcs = 64;
 // LDS words per cell of the fused step's gradient array: the 18 components

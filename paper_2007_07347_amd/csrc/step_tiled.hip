@@ -458,24 +458,17 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
     step_tile<D, DEV>(m, tl, s, lagged, t);
 }
 
-// Batched step: the tiles of all instances form one sequence (instance k owns
-// [tile_begin[k], tile_begin[k + 1])); the grid covers a fixed capacity and
-// the live count is read from the device table, so the table can change
-// between launches of a captured graph.  parity selects each instance's
-// ping-pong buffers: it reads buffer (parity0 ^ parity).
+// Batched step: the tiles of all instances form one sequence; the grid covers
+// a fixed capacity and each block reads its member and local tile from the
+// device map (one load; member -1 past the live tiles), so the table can
+// change between launches of a captured graph.  parity selects each
+// instance's ping-pong buffers: it reads buffer (parity0 ^ parity).
 template <int D, bool DEV>
 __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
 {
-    const int total = tab.count[1];
-    const int cap = (int)gridDim.x;
-    const int gt = xcd_tile(cap);
-    if (gt >= total) return;
-    int lo = 0, hi = tab.count[0] - 1;          // last k with tile_begin[k] <= gt
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (tab.tile_begin[mid] <= gt) lo = mid; else hi = mid - 1;
-    }
-    const BatchInst &in = tab.inst[lo];
+    const int2 e = tab.tmap[xcd_tile((int)gridDim.x)];
+    if (e.x < 0) return;
+    const BatchInst &in = tab.inst[e.x];
     const int p = in.parity0 ^ parity;
     DevState s;
     s.W = in.W[p]; s.G = in.G[p]; s.Wo = in.W[p ^ 1]; s.Go = in.G[p ^ 1];
@@ -483,7 +476,7 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
     s.fo = reinterpret_cast<double *>(in.f[p ^ 1]);
     s.f32 = reinterpret_cast<const float *>(in.f[p]);
     s.fo32 = reinterpret_cast<float *>(in.f[p ^ 1]);
-    step_tile<D, DEV>(in.m, in.t, s, in.lagged, gt - tab.tile_begin[lo]);
+    step_tile<D, DEV>(in.m, in.t, s, in.lagged, e.y);
 }
 
 }  // namespace
@@ -513,7 +506,7 @@ hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState
 hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity, int cap_tiles, size_t lds,
                              int block, hipStream_t st)
 {
-    const dim3 grid((unsigned)((cap_tiles + kXcds - 1) / kXcds * kXcds)), blk(block);
+    const dim3 grid((unsigned)batch_grid(cap_tiles)), blk(block);
     if (D <= 3) {
         if (dev32) hipLaunchKernelGGL((k_step_batch<3, true>), grid, blk, lds, st, tab, parity);
         else hipLaunchKernelGGL((k_step_batch<3, false>), grid, blk, lds, st, tab, parity);
