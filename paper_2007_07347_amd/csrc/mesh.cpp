@@ -121,10 +121,9 @@ bool build_tiles(MeshBuild &out, std::vector<std::pair<size_t, size_t>> parts)
     const int32_t nc = out.nc, D = out.D;
     out.n_tiles = (int32_t)parts.size();
     // Tiles with a boundary face do more work (boundary states in phases 2 and
-    // 3).  Each XCD takes a contiguous range of tiles and starts them in order,
-    // so within each range those tiles go first.
+    // 3).  Each XCD takes a contiguous range of tiles (xcd_range_start) and
+    // starts them in order, so within each range those tiles go first.
     {
-        const size_t per = (parts.size() + kXcds - 1) / kXcds;
         auto at_boundary = [&](const std::pair<size_t, size_t> &p) {
             for (size_t c = p.first; c < p.second; c++)
                 for (int32_t s = 0; s < D; s++) {
@@ -133,8 +132,10 @@ bool build_tiles(MeshBuild &out, std::vector<std::pair<size_t, size_t>> parts)
                 }
             return false;
         };
-        for (size_t lo = 0; lo < parts.size(); lo += per)
-            std::stable_partition(parts.begin() + lo, parts.begin() + std::min(lo + per, parts.size()), at_boundary);
+        const int32_t n = (int32_t)parts.size();
+        for (int32_t x = 0; x < kXcds; x++)
+            std::stable_partition(parts.begin() + xcd_range_start(n, x), parts.begin() + xcd_range_start(n, x + 1),
+                                  at_boundary);
     }
     out.tile_hdr.assign((size_t)out.n_tiles * 8, 0);
     std::vector<std::vector<int32_t>> locals(out.n_tiles);

@@ -2,6 +2,8 @@
 // arrays in the library's (optionally RCM) order.
 #pragma once
 
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -77,6 +79,13 @@ constexpr int32_t kXcds = 8;
 // Workgroups of a batched launch with room for cap_tiles tiles (a multiple of
 // kXcds, so each XCD has the same number of tile slots).
 inline int32_t batch_grid(int32_t cap_tiles) { return (cap_tiles + kXcds - 1) / kXcds * kXcds; }
+// The single-instance fused step launches one workgroup per tile; workgroup b
+// runs on XCD b % kXcds, so XCD x gets n / kXcds tiles, one more if
+// x < n % kXcds, and takes the contiguous range that starts here.
+__host__ __device__ inline int32_t xcd_range_start(int32_t n, int32_t x)
+{
+    return x * (n / kXcds) + (x < n % kXcds ? x : n % kXcds);
+}
 // Boundary-condition entries the fused step keeps in LDS (more: two-kernel step).
 constexpr int32_t kMaxTileBcs = 64;
 // LDS words per cell of the fused step's gradient array: the 18 components

@@ -443,18 +443,22 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
 }
 
 // Workgroups are dealt round-robin to the XCDs: block b runs on XCD b % 8.
-// Give XCD x the contiguous range [x * per, (x + 1) * per) of a tile sequence.
+// Give XCD x the contiguous range [x * per, (x + 1) * per) of a sequence of
+// slots (the grid a multiple of 8).
 __device__ __forceinline__ int xcd_tile(int n)
 {
     const int per = (n + kXcds - 1) / kXcds;
     return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
 }
 
+// One block per tile: the tile of this block, XCD by XCD in contiguous ranges
+// (xcd_range_start).  It follows from the block index and the grid size
+// alone, so the first requests wait for nothing but the table pointers.
 template <int D, bool DEV>
 __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevState s, int lagged)
 {
-    const int t = xcd_tile(tl.n_tiles);
-    if (t >= tl.n_tiles) return;
+    const int x = (int)(blockIdx.x % kXcds);
+    const int t = xcd_range_start((int)gridDim.x, x) + (int)(blockIdx.x / kXcds);
     step_tile<D, DEV>(m, tl, s, lagged, t);
 }
 
@@ -486,7 +490,7 @@ size_t step_tiled_lds_bytes(const DevTiles &t, int dev32, int n_bc)
     return tile_lds_bytes(t.nl_max, t.na_max, n_bc, dev32 ? sizeof(float) : sizeof(double));
 }
 
-static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)((t.n_tiles + kXcds - 1) / kXcds * kXcds); }
+static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)t.n_tiles; }
 
 hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
                              int block, hipStream_t st)
