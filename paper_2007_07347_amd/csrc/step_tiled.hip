@@ -153,6 +153,50 @@ __device__ __forceinline__ void boundary_state_t(const double *sbc, int e, doubl
 }
 
 
+// Least-squares gradient of fbar+ for velocities [I0, I1) of local cell c:
+// sum over its stencil of w (value - fbar+_c), boundary points carrying
+// fbar+_b - fbar+_c = feq(rho_b, u_b) - feq(W_c).
+template <int I0, int I1, int D, typename R>
+__device__ __forceinline__ void gradient_cell(const R *sfbp, R *ssg, const double *sW, const double *sbc, int P, int c,
+                                              const int *la2, const R *wx2, const R *wy2)
+{
+    constexpr int N = I1 - I0, SG = kGradStride;
+    R ax[N], ay[N], fc[N];
+    static_for<N>([&](auto K) {
+        ax[K] = 0;
+        ay[K] = 0;
+        fc[K] = sfbp[c * 9 + I0 + K];
+    });
+#pragma unroll
+    for (int sl = 0; sl < D; sl++) {
+        const int la = la2[sl];
+        if (la == -1) continue;
+        if (la >= 0) {
+            static_for<N>([&](auto K) {
+                const R df = sfbp[la * 9 + I0 + K] - fc[K];
+                ax[K] += wx2[sl] * df;
+                ay[K] += wy2[sl] * df;
+            });
+        } else {
+            const double r = sW[c], ux = sW[3 * P + c], uy = sW[4 * P + c];
+            double rb, ub, vb;
+            boundary_state_t(sbc, -2 - la, r, ux, uy, rb, ub, vb);
+            const double uu = ux * ux + uy * uy, uub = ub * ub + vb * vb;
+            static_for<N>([&](auto K) {
+                constexpr int i = I0 + K;
+                const R df = (R)(feq_c<cEx[i], cEy[i]>(cW[i], rb, ub, vb, uub) -
+                                 feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu));
+                ax[K] += wx2[sl] * df;
+                ay[K] += wy2[sl] * df;
+            });
+        }
+    }
+    static_for<N>([&](auto K) {
+        ssg[c * SG + I0 + K] = ax[K];
+        ssg[c * SG + 9 + I0 + K] = ay[K];
+    });
+}
+
 // One time step of tile t of one instance (the whole workgroup takes part).
 template <int D, bool DEV>
 __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, const DevState &s, int lagged, int t)
@@ -200,7 +244,14 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     const int lc3c = lc3 < PT ? lc3 : 0;
     const int fc3 = lfc[sl3c * PT + lc3c];
     __builtin_amdgcn_sched_barrier(0);
-    const int t2 = tid < P1 ? tid : 0;
+    // phase 2 cell of this thread: in FP64, with two waves or more and at
+    // least twice as many threads as tile and first-ring cells, the two halves
+    // of the workgroup take the same cells, velocities 0..4 and 5..8 (in the
+    // deviation form the gradient is cheap enough that one half does it all)
+    const int half = (int)blockDim.x >> 1;
+    const bool split = !DEV && half >= 64 && P1 <= half;
+    const int c2 = split && tid >= half ? tid - half : tid;
+    const int t2 = c2 < P1 ? c2 : 0;
     int la2[D];
     R wx2[D], wy2[D];
 #pragma unroll
@@ -226,7 +277,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // second-ring cells, for the masks of each phase
     const int *hd = tl.hdr + 8 * t;
     const int g0 = hd[0], nt = hd[1], na = nt + hd[2], nl = na + hd[3];
-    const bool p1 = tid < nl, p2 = tid < na, p3 = lc3 < nt;
+    const bool p1 = tid < nl, p2 = c2 < na, p3 = lc3 < nt;
 #pragma unroll
     for (int sl = 0; sl < D; sl++) la2[sl] = p2 ? la2[sl] : -1;
     const int g3 = g0 + (p3 ? lc3 : 0);
@@ -265,40 +316,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
 
     // ---- phase 2: gradients of the tile and its first ring
     if (p2) {
-        R ax[9], ay[9], fc[9];
-#pragma unroll
-        for (int i = 0; i < 9; i++) { ax[i] = 0; ay[i] = 0; fc[i] = sfbp[tid * 9 + i]; }
-#pragma unroll
-        for (int sl = 0; sl < D; sl++) {
-            const int la = la2[sl];
-            if (la == -1) continue;
-            if (la >= 0) {
-#pragma unroll
-                for (int i = 0; i < 9; i++) {
-                    const R df = sfbp[la * 9 + i] - fc[i];
-                    ax[i] += wx2[sl] * df;
-                    ay[i] += wy2[sl] * df;
-                }
-            } else {
-                // boundary point: fbar+_b - fbar+_c = feq(rho_b, u_b) - feq(W_c)
-                const double r = sW[tid], ux = sW[3 * P + tid], uy = sW[4 * P + tid];
-                double rb, ub, vb;
-                boundary_state_t(sbc, -2 - la, r, ux, uy, rb, ub, vb);
-                const double uu = ux * ux + uy * uy, uub = ub * ub + vb * vb;
-                static_for<9>([&](auto I) {
-                    constexpr int i = I;
-                    const R df = (R)(feq_c<cEx[i], cEy[i]>(cW[i], rb, ub, vb, uub) -
-                                     feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu));
-                    ax[i] += wx2[sl] * df;
-                    ay[i] += wy2[sl] * df;
-                });
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < 9; i++) {
-            ssg[tid * SG + i] = ax[i];
-            ssg[tid * SG + 9 + i] = ay[i];
-        }
+        if (!split) gradient_cell<0, 9, D>(sfbp, ssg, sW, sbc, P, c2, la2, wx2, wy2);
+        else if (tid < half) gradient_cell<0, 5, D>(sfbp, ssg, sW, sbc, P, c2, la2, wx2, wy2);
+        else gradient_cell<5, 9, D>(sfbp, ssg, sW, sbc, P, c2, la2, wx2, wy2);
     }
     __syncthreads();
 
