@@ -1,0 +1,62 @@
+"""The fused step's result does not depend on its launch schedule.
+
+The arithmetic of every cell is the same whatever tile it falls in: fbar+ and
+the gradient per cell, each face from the same operands on both sides, the
+per-cell sums in slot order.  Tile size, workgroup size, the order of cells
+and tiles (boundary tiles first, rows inside tiles) and the split of the FP64
+gradient over the two halves of a workgroup only move work around, so every
+schedule the autotuner may pick must give bit-identical states."""
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=float)
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=float)
+SCHEDULES = [(16, 64), (16, 128), (32, 128), (16, 256), (32, 256), (64, 256)]
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_07347_amd import sdugks
+    return sdugks
+
+
+def _free_slip():
+    mesh, bcs = meshgen.couette(6, 14)
+    bcs = list(bcs)
+    bcs[0] = meshgen.bc(meshgen.SYMMETRY)
+    return meshgen.rotate(mesh, bcs, 0.41)
+
+
+CASES = {
+    "cavity_48": (lambda: meshgen.cavity(48), dict(nu=1e-3)),
+    "ogrid_64x24": (lambda: meshgen.cylinder_ogrid(64, 24, seed=5), dict(nu=2.5e-3, u0=0.1)),
+    "hybrid_ogrid_60x20": (lambda: meshgen.cylinder_ogrid(60, 20, seed=8, quad_layers=5), dict(nu=2.5e-3, u0=0.1)),
+    "periodic_tri_20": (lambda: meshgen.jittered_periodic_triangles(20, seed=3), dict(nu=4e-3)),
+    "symmetry_couette_rot": (_free_slip, dict(nu=1e-2)),
+}
+
+
+@pytest.mark.parametrize("precision", ["FP64", "FP32DEV"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_every_schedule_gives_the_same_bits(sd, name, precision):
+    mk, kw = CASES[name]
+    mesh, bcs = mk()
+    ref = None
+    for tc, bt in SCHEDULES:
+        s = sd.Solver(mesh, bcs, cfl=0.5, precision=getattr(sd, precision), tile_cells=tc, block_threads=bt, **kw)
+        f, _, _ = meshgen.random_state(s.n_cells, seed=41, amp=0.02)
+        s.set_state(f, np.c_[f.sum(1), f @ EX, f @ EY])
+        s.step(60)
+        st = s.state()
+        s.close()
+        if ref is None:
+            ref = st
+            continue
+        for a, b in zip(st, ref):
+            assert np.array_equal(a, b), (name, precision, tc, bt)
