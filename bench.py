@@ -15,11 +15,14 @@ loop; steady drag, lift, stagnation pressure and recirculation length of the
 circular cylinder at Re = 10, 20, 40 and its Strouhal number and mean drag at
 Re = 60, 80, 100; the original half-step DUGKS against the simplified
 scheme (cost per step on the headline cavity, shear-wave accuracy, largest
-stable CFL against Dt/tau); the HBM roofline of the step kernel; and the CPU
-oracle timed on a bounded sample of the headline workload.
+stable CFL against Dt/tau); the share of the HBM peak on a 2048 x 2048 cavity
+whose working set is far beyond the Infinity Cache; the HBM roofline of the
+step kernel; and the CPU oracle timed on a bounded sample of the headline
+workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
     python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
+    python bench.py --large-only              (only the 2048 x 2048 cavity, for HBM counters)
 """
 from __future__ import annotations
 
@@ -55,6 +58,8 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="headline workload only")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
+    p.add_argument("--large-only", action="store_true",
+                   help="only the 2048 x 2048 cavity (working set above 2 GB), for HBM counters")
     return p.parse_args()
 
 
@@ -358,6 +363,38 @@ def original_scheme_form(sdugks, meshgen, sched, steps=3000):
                           "dt_over_tau": list(ratios), "rows": stability}}
 
 
+def large_form(sdugks, meshgen, n=2048, steps=100, warmup=20):
+    """Lid-driven cavity on n x n tanh quads (n = 2048: 4.2M cells, device
+    state above 2 GB, far beyond the 256 MB Infinity Cache), Re 1000, FP64 and
+    FP32 deviation, 64-cell tiles: MLUPS and the step's share of the HBM peak,
+    from the algorithmic bytes and, while the committed counters match the
+    kernel, from the measured HBM traffic."""
+    import torch
+    mesh, bcs = meshgen.cavity(n, beta=1.5, U=0.1)
+    out = {"workload": f"lid-driven cavity {n}x{n} tanh(1.5) quads, Re 1000, CFL 0.5, tiles of 64 cells, "
+                       f"{steps} steps after {warmup}"}
+    for prec, pname in ((sdugks.FP64, "f64"), (sdugks.FP32DEV, "fp32dev")):
+        kw = dict(nu=1e-4, cfl=0.5, precision=prec, tile_cells=64, block_threads=256)
+        s = sdugks.Solver(mesh, bcs, **kw)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        ms = time_steps(s.step, steps) / steps
+        nc = s.n_cells
+        s.close()
+        alg = ALG_BYTES[pname] * nc / (ms / 1e3) / 1e9
+        e = {"mlups": round(nc / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
+             "working_set_GB": round(sdugks.state_bytes(mesh, bcs, **kw) / 1e9, 2),
+             "achieved_GBs": round(alg, 1), "frac_of_hbm_peak": round(alg / HBM_PEAK_GBS, 4)}
+        t = measured_traffic(f"cavity{n}_{pname}")
+        if t is not None:
+            e["traffic_bytes_per_launch"] = t
+            e["measured_GBs"] = round(t / (ms / 1e3) / 1e9, 1)
+            e["measured_frac_of_hbm_peak"] = round(t / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        out[pname] = e
+        progress(f"large cavity {pname}: {e['mlups']} MLUPS, {e['frac_of_hbm_peak']} of HBM peak (algorithmic)")
+    return out
+
+
 def cpu_baseline(mesh, bcs, kw, target_s):
     import oracle
     kw = {k: v for k, v in kw.items() if k in ("nu", "cfl")}
@@ -386,6 +423,9 @@ def main():
         return
     import meshgen
     from paper_2007_07347_amd import autotune, sdugks
+    if a.large_only:
+        print(json.dumps({"large": large_form(sdugks, meshgen)}), flush=True)
+        return
 
     s, mesh, bcs, kw, sched, nc, ms, wall, eps, kt = headline(sdugks, autotune, meshgen, a, sdugks.FP64)
     mlups = nc * a.steps / (ms / 1e3) / 1e6
@@ -431,6 +471,7 @@ def main():
         progress("serving trace done")
         out["cylinder"] = cylinder_form(meshgen)
         out["original_scheme"] = original_scheme_form(sdugks, meshgen, sched)
+        out["large"] = large_form(sdugks, meshgen)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, bcs, kw, a.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -111,6 +111,45 @@ def test_converged_cavity_velocity_l2(sd):
     assert abs(drift32 - drift64) <= 1e-6
 
 
+def test_cylinder_200k_window(sd, oracle_mod):
+    """Flow past a cylinder at Re = 40 on the 400 x 250 jittered triangle
+    O-grid (200,000 cells), far-field inflow 0.1, in the deviation form: the
+    first 12 steps of the full-size case against the FP64 oracle started from
+    the same (FP32-rounded) state."""
+    mesh, bcs = meshgen.cylinder_ogrid(400, 250, seed=0)
+    kw = dict(nu=0.1 / 40, cfl=0.5, u0=0.1)
+    g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, **kw)
+    o = oracle_mod.Oracle(mesh, bcs, **kw)
+    assert g.n_cells == 200000
+    f0, W0, _ = g.state()
+    o.set_state(f0, W0)
+    g.step(12)
+    o.step(12)
+    fg, Wg, _ = g.state()
+    fo, Wo, _ = o.state()
+    ef, er, em = rel_linf(fg, fo), rel_linf(Wg[:, 0], Wo[:, 0]), rel_linf(Wg[:, 1:], Wo[:, 1:])
+    print(f"cylinder200k fp32dev: f {ef:.2e} rho {er:.2e} mom {em:.2e}", flush=True)
+    assert ef <= 2e-6 and er <= 2e-6 and em <= 2e-6
+
+
+def test_cylinder_200k_against_fp64(sd):
+    """The same case run 20,000 steps from the free stream (the wake growing
+    behind the cylinder) in both storage forms: the deviation form's velocity
+    within 1e-5 relative L2 of the FP64 solution, mass within 1e-6."""
+    mesh, bcs = meshgen.cylinder_ogrid(400, 250, seed=0)
+    kw = dict(nu=0.1 / 40, cfl=0.5, u0=0.1)
+    g64 = sd.Solver(mesh, bcs, precision=sd.FP64, **kw)
+    g32 = sd.Solver(mesh, bcs, precision=sd.FP32DEV, **kw)
+    g64.step(20000)
+    g32.step(20000)
+    _, u64, v64 = g64.macros()
+    _, u32, v32 = g32.macros()
+    l2 = np.sqrt(((u32 - u64) ** 2 + (v32 - v64) ** 2).sum() / (u64 ** 2 + v64 ** 2).sum())
+    dm = abs(g32.mass() - g64.mass()) / g64.mass()
+    print(f"cylinder200k Re40, 20000 steps: velocity L2 {l2:.2e}, mass {dm:.2e}", flush=True)
+    assert l2 <= 1e-5 and dm <= 1e-6
+
+
 def test_mass_conserved_periodic(sd):
     mesh, bcs = meshgen.jittered_periodic_triangles(24, seed=8)
     g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, nu=0.004, cfl=0.5)
