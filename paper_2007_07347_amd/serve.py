@@ -12,6 +12,12 @@ frees the slot and the memory, and the next queued request is admitted
 before the next chunk: requests that arrive while others run join the
 running batch.
 
+An instance whose residual has stopped falling while still above the
+tolerance (no 20 % gain over `stall_checks` checks) is handed to the
+backend's optional escalate(): the GPU backend continues it from its current
+state in FP64 storage, whose residual floor lies far below the FP32
+deviation form's, when the larger instance fits the remaining budget.
+
 Time-to-steady of a request = completion time - arrival time (queueing
 included).  The backend interface keeps the policy testable without a GPU:
 
@@ -20,6 +26,8 @@ included).  The backend interface keeps the policy testable without a GPU:
                                               .macros(), .close(), .n_cells
     backend.batch(instances) -> batch         batch.step(n), .set_members(list),
                                               .close()
+    backend.escalate(req, inst, room)         optional: (instance, bytes) that
+        -> (instance, int) or None            continues inst, or None
 """
 from __future__ import annotations
 
@@ -67,10 +75,12 @@ class Server:
     tol:          residual that counts as steady.
     step_cap:     steps after which an instance is retired as not converged.
     keep_macros:  copy (rho, u, v) out of each retired instance.
+    stall_checks: checks without a 20 % fall of the residual after which a
+                  request above the tolerance is escalated (0: never).
     """
 
     def __init__(self, backend, budget_bytes, max_slots=64, interval=1000, tol=1e-7, step_cap=200_000,
-                 keep_macros=False, clock: Callable[[], float] = time.perf_counter,
+                 keep_macros=False, stall_checks=8, clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep):
         self.backend = backend
         self.budget = int(budget_bytes)
@@ -79,6 +89,7 @@ class Server:
         self.tol = float(tol)
         self.step_cap = int(step_cap)
         self.keep_macros = keep_macros
+        self.stall_checks = int(stall_checks)
         self.clock = clock
         self.sleep = sleep
         self.log: List[tuple] = []          # (time, event, rid, extra)
@@ -87,7 +98,7 @@ class Server:
         """Serve a finite trace; returns (results in request order, stats)."""
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: List[Request] = []
-        active = []                         # [req, instance, bytes, admitted_at, steps]
+        active = []                         # [req, instance, bytes, admitted_at, steps, best, stalled, escalated]
         results = {}
         used = 0
         batch = None
@@ -114,7 +125,7 @@ class Server:
                 queue.pop(0)
                 inst = self.backend.create(req)
                 used += need
-                active.append([req, inst, need, now(), 0])
+                active.append([req, inst, need, now(), 0, math.inf, 0, False])
                 members_changed = True
                 self.log.append((now(), "admit", req.rid, need))
             if not active:
@@ -132,8 +143,9 @@ class Server:
                 cell_updates += a[1].n_cells * self.interval
             # poll every instance, then change the membership once, then free
             keep, retired = [], []
+            can_escalate = self.stall_checks > 0 and hasattr(self.backend, "escalate")
             for a in active:
-                req, inst, need, t_adm, steps = a
+                req, inst, need, t_adm, steps = a[:5]
                 status = None
                 try:
                     eps = inst.residual()
@@ -147,6 +159,18 @@ class Server:
                     elif steps >= self.step_cap:
                         status = "not_converged"
                 if status is None:
+                    if eps < 0.8 * a[5]:
+                        a[5], a[6] = eps, 0
+                    else:
+                        a[6] += 1
+                    if can_escalate and not a[7] and a[6] >= self.stall_checks:
+                        got = self.backend.escalate(req, inst, self.budget - used + need)
+                        if got is not None:
+                            new, new_need = got
+                            used += new_need - need
+                            a[1], a[2], a[5], a[6], a[7] = new, new_need, math.inf, 0, True
+                            retired.append(inst)
+                            self.log.append((now(), "escalate", req.rid, steps))
                     keep.append(a)
                     continue
                 macros = inst.macros() if (self.keep_macros and status != "diverged") else None
@@ -235,7 +259,8 @@ class SequentialServer(Server):
 
 class GpuBackend:
     """Backend on libsdugks: one solver per request (its device memory a torch
-    tensor of sdugks_state_bytes), one batch for all admitted solvers."""
+    tensor of sdugks_state_bytes), one batch for all admitted solvers; a
+    stalled FP32-deviation solver is continued by an FP64 one."""
 
     def __init__(self, precision=None, **defaults):
         from . import sdugks
@@ -257,3 +282,15 @@ class GpuBackend:
 
     def batch(self, instances):
         return self.sd.Batch(instances)
+
+    def escalate(self, req, inst, room):
+        kw = self._kw(req)
+        if kw["precision"] != self.sd.FP32DEV:
+            return None
+        kw["precision"] = self.sd.FP64
+        need = self.sd.state_bytes(req.mesh, req.bcs, **kw)
+        if need > room:
+            return None
+        new = self.sd.Solver(req.mesh, req.bcs, **kw)
+        new.set_state(*inst.state())
+        return new, need

@@ -1,6 +1,7 @@
 """Serving loop on the GPU: requests admitted by HBM budget into one running
 batch give, bit for bit, the result of the same request solved alone for the
-same number of steps."""
+same number of steps; a request whose FP32-deviation residual stalls above
+the tolerance is continued in FP64 and converges."""
 import numpy as np
 import pytest
 
@@ -19,7 +20,8 @@ def test_served_results_equal_alone():
           for r in trace]
     backend = serve.GpuBackend()
     budget = sum(backend.bytes(q) for q in rq[:3])          # at most about three at a time
-    srv = serve.Server(backend, budget_bytes=budget, interval=500, tol=1e-7, step_cap=6000, keep_macros=True)
+    srv = serve.Server(backend, budget_bytes=budget, interval=500, tol=1e-7, step_cap=6000, keep_macros=True,
+                       stall_checks=0)
     res, stats = srv.run(rq)
     print(stats, flush=True)
     assert stats["requests"] == 8 and stats["rejected"] == 0
@@ -32,3 +34,32 @@ def test_served_results_equal_alone():
         for a, b in zip(r.macros, s.macros()):
             assert np.array_equal(a, b)
         s.close()
+
+
+def test_stalled_request_continues_in_fp64():
+    """Cylinder at Re 20 on a coarse O-grid: the deviation form's residual
+    floors above 1e-7, the server continues the request in FP64 storage from
+    its current state, and it converges to the FP64 solution."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2007_07347_amd import sdugks, serve
+    mesh, bcs = meshgen.cylinder_ogrid(64, 24, seed=1)
+    params = dict(nu=0.1 / 20, cfl=0.5, u0=0.1)
+    q = serve.Request(0, 0.0, mesh, bcs, params, "cylinder", 2 * 64 * 24)
+    srv = serve.Server(serve.GpuBackend(), budget_bytes=1 << 30, interval=1000, tol=1e-7, step_cap=400_000,
+                       keep_macros=True, stall_checks=8)
+    (r,), stats = srv.run([q])
+    print(r.status, r.steps, r.residual, [e for e in srv.log if e[1] == "escalate"], flush=True)
+    assert r.status == "converged" and r.residual <= 1e-7
+    assert [e[1] for e in srv.log].count("escalate") == 1
+    ref = sdugks.Solver(mesh, bcs, precision=sdugks.FP64, **params)
+    eps = 1.0
+    while eps > 1e-8:
+        ref.step(5000)
+        eps = ref.residual()
+    _, u, v = ref.macros()
+    _, us, vs = r.macros
+    l2 = np.sqrt(((us - u) ** 2 + (vs - v) ** 2).sum() / (u ** 2 + v ** 2).sum())
+    print("velocity L2 against FP64 alone", l2, flush=True)
+    assert l2 <= 1e-5
+    ref.close()

@@ -215,3 +215,73 @@ def test_results_same_alone_and_in_the_mix(oracle_mod):
         for a, b in zip(r.macros, o.macros()):
             assert np.array_equal(a, b)
     assert stats["converged"] + stats["not_converged"] == 5
+
+
+class PlateauInst(FakeInst):
+    """Like the FP32 deviation form: the residual falls tenfold per 1000 steps
+    down to a floor of 1e-6, above the tolerance."""
+
+    def residual(self):
+        assert not self.closed
+        return max(1e-6, 10.0 ** (-self.steps / 1000.0))
+
+
+class PreciseInst(FakeInst):
+    """The FP64 continuation: converges 3000 steps after it takes over."""
+
+    def __init__(self, req, clock, log, start):
+        super().__init__(req, clock, log)
+        self.start = self.steps = start
+
+    def residual(self):
+        assert not self.closed
+        return 1e-9 if self.steps >= self.start + 3000 else 1e-6
+
+
+class EscalatingBackend(FakeBackend):
+    def __init__(self, clock):
+        super().__init__(clock)
+        self.escalated, self.old = [], []
+
+    def create(self, req):
+        inst = PlateauInst(req, self.clock, self.log)
+        self.live[req.rid] = inst
+        return inst
+
+    def escalate(self, req, inst, room):
+        need = 2 * self.bytes(req)
+        if need > room:
+            return None
+        new = PreciseInst(req, self.clock, self.log, inst.steps)
+        self.escalated.append((req.rid, inst.steps))
+        self.old.append(inst)
+        self.live[req.rid] = new
+        return new, need
+
+
+def _serve_escalating(budget, **kw):
+    clock = SimClock()
+    be = EscalatingBackend(clock)
+    srv = Server(be, budget_bytes=budget, clock=clock, sleep=clock.sleep, interval=1000, tol=1e-7,
+                 stall_checks=4, **kw)
+    res, stats = srv.run(reqs([(0.0, 100, {}), (0.0, 100, {})]))
+    return res, stats, srv, be
+
+
+def test_stalled_request_escalated_and_converges():
+    """The residual floors at step 6000; four checks later (step 10000) the
+    request continues in the precise form and converges 3000 steps after."""
+    res, stats, srv, be = _serve_escalating(budget=10**6, step_cap=50_000)
+    assert [r.status for r in res] == ["converged", "converged"]
+    assert [s for _, s in be.escalated] == [10_000, 10_000]
+    assert [r.steps for r in res] == [13_000, 13_000]
+    assert all(inst.closed for inst in be.old) and all(inst.closed for inst in be.live.values())
+    assert sum(ev == "escalate" for _, ev, _, _ in srv.log) == 2
+
+
+def test_escalation_needs_room_in_the_budget():
+    """The precise form needs twice the bytes: with room for neither request
+    to double, both run on to the step cap."""
+    res, stats, srv, be = _serve_escalating(budget=25_000, step_cap=20_000)
+    assert be.escalated == []
+    assert [r.status for r in res] == ["not_converged", "not_converged"]
