@@ -191,8 +191,10 @@ def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
 
 def serving(meshgen, seed=7, n_requests=24, step_cap=150_000):
     """Continuous-batching serving loop on a finite seeded trace (Poisson
-    arrivals at 20 per second, Couette / cavity / cylinder requests) against
-    the plain per-case FP64 loop on the same trace."""
+    arrivals at 20 per second, Couette / cavity / cylinder requests; FP32
+    deviation storage, a request whose residual stalls above the tolerance
+    continued in FP64) against the plain per-case FP64 loop on the same
+    trace."""
     from paper_2007_07347_amd import sdugks, serve
     trace = meshgen.serving_trace(seed=seed, n_requests=n_requests)
     rq = [serve.Request(r["rid"], r["arrival"], r["mesh"], r["bcs"], r["params"], r["kind"], r["n_cells"])
