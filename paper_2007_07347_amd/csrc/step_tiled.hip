@@ -7,7 +7,9 @@
 //            tile that needs them instead of being stored to memory);
 //   phase 2  least-squares gradient of fbar+ (the LLSR normal equations solved
 //            through precomputed weights A^-1 d; boundary states are points at
-//            the face midpoints) for the tile and its first ring, into LDS;
+//            the face midpoints) for the tile and its first ring, into LDS (in
+//            FP64 the two halves of the workgroup take velocities 0..4 and
+//            5..8 of the same cells when those fit in one half);
 //   phase 3  four lanes per tile cell, one face each: upwind reconstruction at
 //            the foot point (Eq. fbpsource), face macros and equilibrium,
 //            f at the face (Eq. f_t_n+1), mesoscopic and macroscopic fluxes
