@@ -20,7 +20,7 @@ whose working set is far beyond the Infinity Cache; the HBM roofline of the
 step kernel; and the CPU oracle timed on a bounded sample of the headline
 workload.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra | --sections a,b,...]
     python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
     python bench.py --large-only              (only the 2048 x 2048 cavity, for HBM counters)
 """
@@ -47,6 +47,7 @@ RESIDUAL_INTERVAL = 1000
 ALG_BYTES = {"f64": 2 * (72 + 24) + 184, "fp32dev": 2 * (36 + 24) + 184}
 KERNEL_SRC = os.path.join(ROOT, "paper_2007_07347_amd", "csrc", "step_tiled.hip")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+SECTIONS = ("fp32dev", "batch", "serving", "cylinder", "original", "large")
 
 
 def parse():
@@ -56,6 +57,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=300)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="headline workload only")
+    p.add_argument("--sections", default=",".join(SECTIONS),
+                   help="extra sections to run after the headline, comma-separated from " + ",".join(SECTIONS))
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     p.add_argument("--large-only", action="store_true",
@@ -414,6 +417,10 @@ def cpu_baseline(mesh, bcs, kw, target_s):
 
 def main():
     a = parse()
+    unknown = {x for x in a.sections.split(",") if x} - set(SECTIONS)
+    if unknown:
+        print(f"unknown sections: {sorted(unknown)}; choose from {','.join(SECTIONS)}", file=sys.stderr)
+        sys.exit(2)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described, not built.",
               file=sys.stderr)
@@ -457,7 +464,8 @@ def main():
         "wall_s": round(wall, 3),
     }
     s.close()
-    if not a.no_extra:
+    sections = set() if a.no_extra else {x for x in a.sections.split(",") if x}
+    if "fp32dev" in sections:
         s32, _, _, _, sched32, _, ms32, _, _, kt32 = headline(sdugks, autotune, meshgen, a, sdugks.FP32DEV)
         k32 = ms32 / a.steps
         out["fp32dev"] = {"value": round(nc * a.steps / (ms32 / 1e3) / 1e6, 1), "unit": "MLUPS",
@@ -467,12 +475,17 @@ def main():
                           "traffic": measured_traffic("cavity256_fp32dev")}
         s32.close()
         progress("fp32 deviation form done")
+    if "batch" in sections:
         out["batch"] = batch_form(sdugks, autotune, meshgen)
         progress("batched form done")
+    if "serving" in sections:
         out["serving"] = serving(meshgen)
         progress("serving trace done")
+    if "cylinder" in sections:
         out["cylinder"] = cylinder_form(meshgen)
+    if "original" in sections:
         out["original_scheme"] = original_scheme_form(sdugks, meshgen, sched)
+    if "large" in sections:
         out["large"] = large_form(sdugks, meshgen)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(mesh, bcs, kw, a.cpu_seconds)

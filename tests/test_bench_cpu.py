@@ -38,3 +38,11 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_unknown_section_is_refused():
+    """Checked before anything touches the GPU."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--sections", "fp32dev,nope"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
+    assert set(_bench().SECTIONS) == {"fp32dev", "batch", "serving", "cylinder", "original", "large"}
