@@ -35,7 +35,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Byte layout of one handle's device memory.  Everything is carved from one
-// block: per-cell rows are pitched to np = nc rounded up to 64.
+// block: per-cell rows are pitched to np = nc rounded up to 64, plus 64 when
+// that is a multiple of 2048 (rows a large power of two apart start at the
+// same offset modulo the memory channel interleave, so the nine rows of one
+// cell would be read from the same channels).
 struct Layout {
     size_t np = 0;
     size_t off_f[2]{}, off_W[2]{}, off_G[2]{}, off_fbp = 0, off_sg = 0, off_snap = 0;
@@ -54,6 +57,7 @@ Layout make_layout(const MeshBuild &mb, int precision)
 {
     Layout L;
     L.np = ((size_t)mb.nc + 63) / 64 * 64;
+    if (L.np % 2048 == 0) L.np += 64;
     const bool dev = precision == SDUGKS_FP32DEV;
     const size_t row = L.np * sizeof(double), rowf = L.np * (dev ? sizeof(float) : sizeof(double));
     size_t p = 0;

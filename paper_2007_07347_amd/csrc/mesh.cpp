@@ -550,7 +550,7 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lfc.clear(); out.frec.clear(); out.lw.clear();
     if (tiled) {
         if (!build_tiles(out, parts)) BAD("internal: the two views of a face are not exact mirrors");
-        if (tile_lds_bytes(out.nl_max, out.na_max, n_bc) > kTileLdsLimit || out.nl_max > B) {
+        if (tile_lds_bytes(out.nl_max, out.na_max, out.nt_max, n_bc) > kTileLdsLimit || out.nl_max > B) {
             // one thread per local cell and LDS for all of them: bisect into smaller tiles
             if (T <= 4) BAD("mesh too irregular for the fused step's tiles");
             sdugks_params smaller = *prm;

@@ -92,12 +92,15 @@ constexpr int32_t kMaxTileBcs = 64;
 // and one pad, so that consecutive cells fall on different LDS banks (an odd
 // number of words in FP32, an odd number of word pairs in FP64).
 constexpr int32_t kGradStride = 19;
-// LDS bytes of one workgroup of the fused step: per local cell W, u and fbar+,
-// per tile or first-ring cell the gradient (elem bytes: 8 FP64, 4 deviation
-// form), then the boundary-condition table (4 doubles per entry).
-inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max, int32_t n_bc, size_t elem = 8)
+// LDS bytes of one workgroup of the fused step: rho and u of every tile or
+// first-ring cell and the momentum of every tile cell (FP64), fbar+ of every
+// local cell and the gradient of every tile or first-ring cell (elem bytes:
+// 8 FP64, 4 deviation form), then the boundary-condition table (4 doubles
+// per entry).
+inline size_t tile_lds_bytes(int32_t nl_max, int32_t na_max, int32_t nt_max, int32_t n_bc, size_t elem = 8)
 {
-    const size_t head = 5 * (size_t)nl_max * 8 + (9 * (size_t)nl_max + kGradStride * (size_t)na_max) * elem;
+    const size_t head = (3 * (size_t)na_max + 2 * (size_t)nt_max) * 8 +
+                        (9 * (size_t)nl_max + kGradStride * (size_t)na_max) * elem;
     return (head + 15) / 16 * 16 + 32 * (size_t)n_bc;
 }
 constexpr size_t kTileLdsLimit = 64 * 1024;

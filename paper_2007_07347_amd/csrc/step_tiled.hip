@@ -159,7 +159,7 @@ __device__ __forceinline__ void boundary_state_t(const double *sbc, int e, doubl
 // sum over its stencil of w (value - fbar+_c), boundary points carrying
 // fbar+_b - fbar+_c = feq(rho_b, u_b) - feq(W_c).
 template <int I0, int I1, int D, typename R>
-__device__ __forceinline__ void gradient_cell(const R *sfbp, R *ssg, const double *sW, const double *sbc, int P, int c,
+__device__ __forceinline__ void gradient_cell(const R *sfbp, R *ssg, const double *sW, const double *sbc, int P1, int c,
                                               const int *la2, const R *wx2, const R *wy2)
 {
     constexpr int N = I1 - I0, SG = kGradStride;
@@ -180,7 +180,7 @@ __device__ __forceinline__ void gradient_cell(const R *sfbp, R *ssg, const doubl
                 ay[K] += wy2[sl] * df;
             });
         } else {
-            const double r = sW[c], ux = sW[3 * P + c], uy = sW[4 * P + c];
+            const double r = sW[c], ux = sW[P1 + c], uy = sW[2 * P1 + c];
             double rb, ub, vb;
             boundary_state_t(sbc, -2 - la, r, ux, uy, rb, ub, vb);
             const double uu = ux * ux + uy * uy, uub = ub * ub + vb * vb;
@@ -208,15 +208,19 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     const int P = tl.nl_max, P1 = tl.na_max, PT = tl.nt_max;
     const int np = m.np;
     const int tid = threadIdx.x;
-    double *sW = smem;                                        // [5][P]: rho, rho u, rho v, u, v
+    // macros: rho, u, v of the tile and first-ring cells [3][P1] (the
+    // boundary states need them), rho u, rho v of the tile cells [2][PT] (the
+    // update needs them); nothing for the second ring
+    double *sW = smem;
+    double *sM = smem + 3 * P1;
     // per cell: fbar+ [P][9] (deviation in DEV) and its gradient [P1][SG]
     // (x components 0..8, y components 9..17, one pad); cell-major, so the
     // velocity and component are constant offsets of one per-cell address
-    R *sfbp = reinterpret_cast<R *>(smem + 5 * P);
+    R *sfbp = reinterpret_cast<R *>(smem + 3 * P1 + 2 * PT);
     R *ssg = sfbp + 9 * P;
     // boundary-condition table [n_bc][4]: type, rho, u, v (16-byte aligned after the gradient)
     constexpr int SG = kGradStride;
-    double *sbc = smem + ((5 * P * 8 + (9 * P + SG * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
+    double *sbc = smem + (((3 * P1 + 2 * PT) * 8 + (9 * P + SG * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
     const int16_t *lfc = tl.lfc + (size_t)t * D * PT;
     using R2 = typename std::conditional<DEV, float2, double2>::type;
@@ -303,11 +307,15 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     if (p1) {
         const double ir = 1.0 / r;
         const double ux = mu * ir, uy = mv * ir, uu = ux * ux + uy * uy;
-        sW[tid] = r;
-        sW[P + tid] = mu;
-        sW[2 * P + tid] = mv;
-        sW[3 * P + tid] = ux;
-        sW[4 * P + tid] = uy;
+        if (tid < na) {
+            sW[tid] = r;
+            sW[P1 + tid] = ux;
+            sW[2 * P1 + tid] = uy;
+        }
+        if (tid < nt) {
+            sM[tid] = mu;
+            sM[PT + tid] = mv;
+        }
         static_for<9>([&](auto I) {
             constexpr int i = I;
             const double fe = feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu) - (DEV ? cW[i] * m.rho0 : 0.0);
@@ -318,9 +326,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
 
     // ---- phase 2: gradients of the tile and its first ring
     if (p2) {
-        if (!split) gradient_cell<0, 9, D>(sfbp, ssg, sW, sbc, P, c2, la2, wx2, wy2);
-        else if (tid < half) gradient_cell<0, 5, D>(sfbp, ssg, sW, sbc, P, c2, la2, wx2, wy2);
-        else gradient_cell<5, 9, D>(sfbp, ssg, sW, sbc, P, c2, la2, wx2, wy2);
+        if (!split) gradient_cell<0, 9, D>(sfbp, ssg, sW, sbc, P1, c2, la2, wx2, wy2);
+        else if (tid < half) gradient_cell<0, 5, D>(sfbp, ssg, sW, sbc, P1, c2, la2, wx2, wy2);
+        else gradient_cell<5, 9, D>(sfbp, ssg, sW, sbc, P1, c2, la2, wx2, wy2);
     }
     __syncthreads();
 
@@ -359,7 +367,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
                 fbar[i] = sn == (R)0 ? (R)0.5 * (rs + ro) : up;
             });
         } else {
-            const double r = sW[lc], ux = sW[3 * P + lc], uy = sW[4 * P + lc];
+            const double r = sW[lc], ux = sW[P1 + lc], uy = sW[2 * P1 + lc];
             double rb, ub, vb;
             boundary_state_t(sbc, -2 - la3, r, ux, uy, rb, ub, vb);
             const double uu = ux * ux + uy * uy, uub = ub * ub + vb * vb;
@@ -415,8 +423,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         double G0 = g0s, G1 = g1s, G2 = g2s;
         if (lagged) { G0 = s.G[g]; G1 = s.G[np + g]; G2 = s.G[2 * np + g]; }
         const double rn = sW[lc] - dtv * G0;
-        const double mxn = sW[P + lc] - dtv * G1;
-        const double myn = sW[2 * P + lc] - dtv * G2;
+        const double mxn = sM[lc] - dtv * G1;
+        const double myn = sM[PT + lc] - dtv * G2;
         if (sl3 == 0) s.Wo[g] = rn;
         if (sl3 == 1) s.Wo[np + g] = mxn;
         if (sl3 == 2) s.Wo[2 * np + g] = myn;
@@ -509,7 +517,7 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
 
 size_t step_tiled_lds_bytes(const DevTiles &t, int dev32, int n_bc)
 {
-    return tile_lds_bytes(t.nl_max, t.na_max, n_bc, dev32 ? sizeof(float) : sizeof(double));
+    return tile_lds_bytes(t.nl_max, t.na_max, t.nt_max, n_bc, dev32 ? sizeof(float) : sizeof(double));
 }
 
 static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)t.n_tiles; }
