@@ -2,6 +2,7 @@
 committed HBM-traffic counters still describe the step kernel, and the
 refusal of more than one GPU."""
 import importlib.util
+import json
 import os
 import subprocess
 import sys
@@ -46,3 +47,21 @@ def test_unknown_section_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
     assert set(_bench().SECTIONS) == {"fp32dev", "batch", "serving", "cylinder", "original", "large"}
+
+
+def test_malformed_schedule_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--schedule", "32"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "--schedule takes two integers" in r.stderr
+
+
+def test_traffic_requires_the_recorded_schedule(tmp_path, monkeypatch):
+    b = _bench()
+    rec = {"w": {"kernel_code_sha1": b.kernel_hash(), "schedule": {"tile_cells": 32, "block_threads": 128},
+                 "bytes_per_launch": 123}}
+    p = tmp_path / "traffic.json"
+    p.write_text(json.dumps(rec))
+    monkeypatch.setattr(b, "TRAFFIC", str(p))
+    assert b.measured_traffic("w", {"tile_cells": 32, "block_threads": 128}) == 123
+    assert b.measured_traffic("w", {"tile_cells": 16, "block_threads": 64}) is None
+    assert b.measured_traffic("w") == 123
