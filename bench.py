@@ -101,6 +101,10 @@ def measured_traffic(workload, schedule=None):
 
 
 def copy_calibration(mb):
+    """Five plain device copies of mb MiB (the launches the counter scaling is
+    taken from), then the HBM bandwidth that plain torch kernels reach on this
+    device: copy, read-only sum (FP64, torch's faster reduction) and fill, 20
+    launches each after one warm-up."""
     import torch
     n = mb * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -108,7 +112,16 @@ def copy_calibration(mb):
     for _ in range(5):
         b.copy_(a)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5}), flush=True)
+
+    def tbs(f, nbytes, reps=20):
+        f()
+        ms = time_steps(lambda k: [f() for _ in range(k)], reps) / reps
+        return round(nbytes / (ms / 1e3) / 1e12, 3)
+
+    print(json.dumps({"copy_bytes_each_way": n * 4, "launches": 5,
+                      "copy_TBs": tbs(lambda: b.copy_(a), 2 * n * 4),
+                      "read_TBs": tbs(lambda: a.view(torch.float64).sum(), n * 4),
+                      "write_TBs": tbs(lambda: b.fill_(1.0), n * 4)}), flush=True)
 
 
 def progress(msg):
