@@ -178,12 +178,12 @@ def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
     rng = np.random.default_rng(seed)
     sizes = meshgen.log_uniform_int(rng, 32, 512, size=n_inst)
     res = rng.uniform(100.0, 5000.0, size=n_inst)
-    solvers, cells = [], 0
-    for n, re in zip(sizes, res):
-        mesh, bcs = meshgen.cavity(int(n), beta=1.5, U=0.1)
-        solvers.append(sdugks.Solver(mesh, bcs, nu=0.1 / re, cfl=0.5, precision=sdugks.FP32DEV,
-                                     tile_cells=32, block_threads=128))
-        cells += int(n) * int(n)
+    problems = [(*meshgen.cavity(int(n), beta=1.5, U=0.1), dict(nu=0.1 / re, cfl=0.5, precision=sdugks.FP32DEV))
+                for n, re in zip(sizes, res)]
+    cells = int(sum(int(n) * int(n) for n in sizes))
+    # one schedule for the whole batched launch, picked by timing the batch
+    sched, table = autotune.autotune_batch(problems)
+    solvers = [sdugks.Solver(mesh, bcs, **sched, **kw) for mesh, bcs, kw in problems]
     b = sdugks.Batch(solvers)
     b.step(20)
     for s in solvers:
@@ -205,7 +205,9 @@ def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
     ms_l = (time.perf_counter() - t0) * 1e3
     b.close()
     out = {"workload": "64 tanh cavities, edge log-uniform in [32, 512], Re uniform in [100, 5000], FP32 deviation",
-           "seed": seed, "cells": cells, "steps": steps,
+           "seed": seed, "cells": cells, "steps": steps, "schedule": sched,
+           "autotune_ms_per_step": {f"{r['tile_cells']}/{r['block_threads']}": (None if r["ms"] is None else
+                                                                             round(r["ms"], 4)) for r in table},
            "batched_mlups": round(cells * steps / (ms_b / 1e3) / 1e6, 1), "batched_ms_per_step": round(ms_b / steps, 4),
            "per_instance_loop_mlups": round(cells * steps / (ms_l / 1e3) / 1e6, 1),
            "per_instance_loop_ms_per_step": round(ms_l / steps, 4)}

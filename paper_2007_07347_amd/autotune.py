@@ -77,3 +77,65 @@ def autotune(mesh, bcs, candidates=None, steps=200, cache=CACHE, refresh=False, 
             json.dump(db, fh, indent=1)
         os.replace(cache + ".tmp", cache)
     return best, table
+
+
+def batch_signature(problems):
+    """Key of a set of batch members: each member's mesh class and parameters."""
+    h = hashlib.sha1()
+    for mesh, bcs, kw in problems:
+        h.update(signature(mesh, kw.get("precision", sdugks.FP64)).encode())
+        h.update(json.dumps(sorted((k, v) for k, v in kw.items() if k != "precision")).encode())
+    return f"batch-{len(problems)}-{h.hexdigest()[:12]}"
+
+
+def time_batch_candidate(problems, tile_cells, block_threads, steps=50, warmup=10):
+    """ms per batched step of all problems, every member on this schedule."""
+    import torch
+    solvers = []
+    try:
+        for mesh, bcs, kw in problems:
+            solvers.append(sdugks.Solver(mesh, bcs, tile_cells=tile_cells, block_threads=block_threads, **kw))
+        b = sdugks.Batch(solvers)
+        try:
+            b.step(warmup)
+            torch.cuda.synchronize()
+            a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            b.step(steps)
+            e.record()
+            torch.cuda.synchronize()
+            return a.elapsed_time(e) / steps
+        finally:
+            b.close()
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def autotune_batch(problems, candidates=None, steps=50, cache=CACHE, refresh=False):
+    """Schedule for a batch: problems is a list of (mesh, bcs, solver keyword
+    arguments without the schedule); each candidate schedule is applied to
+    every member and the batched step timed as a whole (one launch covers all
+    members, so its schedule is one choice).  Returns ({"tile_cells",
+    "block_threads"}, table), cached like autotune()."""
+    key = batch_signature(problems)
+    db = _load_cache(cache) if cache else {}
+    if not refresh and key in db:
+        return db[key]["best"], db[key]["table"]
+    table = []
+    for t, b in (candidates or CANDIDATES):
+        try:
+            ms = time_batch_candidate(problems, t, b, steps=steps)
+        except sdugks.SdugksError as e:
+            table.append({"tile_cells": t, "block_threads": b, "ms": None, "error": str(e)})
+            continue
+        table.append({"tile_cells": t, "block_threads": b, "ms": ms})
+    ok = [r for r in table if r["ms"] is not None]
+    best = min(ok, key=lambda r: r["ms"])
+    best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
+    if cache:
+        db[key] = {"best": best, "table": table}
+        with open(cache + ".tmp", "w") as fh:
+            json.dump(db, fh, indent=1)
+        os.replace(cache + ".tmp", cache)
+    return best, table

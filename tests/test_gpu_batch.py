@@ -126,3 +126,19 @@ def test_batch_refuses_diverged_member(sd):
     b.step(2)
     c.residual()
     b.close()
+
+
+def test_batch_autotuner_times_every_candidate(sd, tmp_path):
+    """The batch autotuner applies each candidate schedule to every member,
+    times the batched step, returns the fastest and caches the choice."""
+    from paper_2007_07347_amd import autotune
+    problems = [(*meshgen.cavity(n), dict(nu=1e-3, cfl=0.5, precision=sd.FP32DEV)) for n in (24, 40, 57)]
+    cands = [(32, 128), (64, 256)]
+    cache = str(tmp_path / "cache.json")
+    best, table = autotune.autotune_batch(problems, candidates=cands, steps=5, cache=cache)
+    assert [(r["tile_cells"], r["block_threads"]) for r in table] == cands
+    assert all(r["ms"] is not None and r["ms"] > 0 for r in table)
+    fastest = min(table, key=lambda r: r["ms"])
+    assert best == {"tile_cells": fastest["tile_cells"], "block_threads": fastest["block_threads"]}
+    again, _ = autotune.autotune_batch(problems, candidates=cands, steps=5, cache=cache)
+    assert again == best

@@ -193,8 +193,10 @@ def test_fused_and_two_kernel_paths_agree(sd):
         assert rel_linf(f, fr) <= 1e-13 and rel_linf(W, Wr) <= 1e-13
 
 
-def test_residual_and_mass_match_oracle(sd, oracle_mod):
-    mesh, bcs = meshgen.cavity(31)
+@pytest.mark.parametrize("n", [31, 64])
+def test_residual_and_mass_match_oracle(sd, oracle_mod, n):
+    """n = 64: 4096 cells, a multiple of 2048, so the rows carry padding."""
+    mesh, bcs = meshgen.cavity(n)
     g = sd.Solver(mesh, bcs, nu=0.001, cfl=0.5)
     o = oracle_mod.Oracle(mesh, bcs, nu=0.001, cfl=0.5)
     assert g.residual() == math.inf and o.residual() == math.inf

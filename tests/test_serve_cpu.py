@@ -285,3 +285,13 @@ def test_escalation_needs_room_in_the_budget():
     res, stats, srv, be = _serve_escalating(budget=25_000, step_cap=20_000)
     assert be.escalated == []
     assert [r.status for r in res] == ["not_converged", "not_converged"]
+
+
+def test_batch_signature_separates_member_sets():
+    import meshgen
+    from paper_2007_07347_amd import autotune
+    a = [(*meshgen.cavity(12), dict(nu=1e-3)), (*meshgen.cavity(16), dict(nu=1e-3))]
+    b = [(*meshgen.cavity(12), dict(nu=1e-3)), (*meshgen.cavity(16), dict(nu=2e-3))]
+    assert autotune.batch_signature(a) == autotune.batch_signature(list(a))
+    assert autotune.batch_signature(a) != autotune.batch_signature(b)
+    assert autotune.batch_signature(a) != autotune.batch_signature(a[:1])
