@@ -45,9 +45,11 @@ RESIDUAL_INTERVAL = 1000
 # 1/V 8, four neighbours x (index 4 + two LSQ weights 16), two faces x
 # (owner/neighbour 8 + l*n 16 + midpoint 16) = 184).
 ALG_BYTES = {"f64": 2 * (72 + 24) + 184, "fp32dev": 2 * (36 + 24) + 184}
+# triangles: three faces per cell, 144 B of geometry per cell instead of 184
+ALG_BYTES_TRI = {"f64": 2 * (72 + 24) + 144, "fp32dev": 2 * (36 + 24) + 144}
 KERNEL_SRC = os.path.join(ROOT, "paper_2007_07347_amd", "csrc", "step_tiled.hip")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-SECTIONS = ("fp32dev", "batch", "serving", "cylinder", "original", "large")
+SECTIONS = ("fp32dev", "batch", "serving", "cylinder", "cylinder200k", "original", "large")
 
 
 def parse():
@@ -392,6 +394,38 @@ def original_scheme_form(sdugks, meshgen, sched, steps=3000):
                           "dt_over_tau": list(ratios), "rows": stability}}
 
 
+def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50):
+    """Throughput on the 200,000-triangle cylinder O-grid (Re 40, far-field
+    inflow 0.1) in FP32 deviation storage and in FP64, each on its autotuned
+    schedule, and the FP32 form's velocity deviation from FP64 after the
+    same steps from rest."""
+    import numpy as np
+    import torch
+    mesh, bcs = meshgen.cylinder_ogrid(400, 250, seed=0)
+    out = {"workload": "circular cylinder, O-grid 400x250 split into 200,000 jittered triangles, r 0.5..20, "
+                       f"Re 40, u_inf 0.1, CFL 0.5, {steps} steps after {warmup} from rest"}
+    uv = {}
+    for prec, pname in ((sdugks.FP32DEV, "fp32dev"), (sdugks.FP64, "f64")):
+        kw = dict(nu=0.1 / 40, cfl=0.5, u0=0.1, precision=prec)
+        sched, _ = autotune.autotune(mesh, bcs, steps=100, **kw)
+        s = sdugks.Solver(mesh, bcs, **sched, **kw)
+        s.step(warmup)
+        torch.cuda.synchronize()
+        ms = time_steps(s.step, steps, s.stream) / steps
+        nc = s.n_cells
+        _, u, v = s.macros()
+        uv[pname] = np.concatenate([u, v])
+        s.close()
+        alg = ALG_BYTES_TRI[pname] * nc / (ms / 1e3) / 1e9
+        out[pname] = {"mlups": round(nc / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5), "schedule": sched,
+                      "alg_bytes_per_cell": ALG_BYTES_TRI[pname], "achieved_GBs": round(alg, 1),
+                      "frac_of_hbm_peak": round(alg / HBM_PEAK_GBS, 4)}
+    d = uv["fp32dev"] - uv["f64"]
+    out["fp32dev_velocity_rel_l2_vs_f64"] = float(np.linalg.norm(d) / np.linalg.norm(uv["f64"]))
+    progress(f"cylinder 200k: fp32dev {out['fp32dev']['mlups']} / f64 {out['f64']['mlups']} MLUPS")
+    return out
+
+
 def large_form(sdugks, meshgen, n=2048, steps=100, warmup=20):
     """Lid-driven cavity on n x n tanh quads (n = 2048: 4.2M cells, device
     state above 2 GB, far beyond the 256 MB Infinity Cache), Re 1000, FP64 and
@@ -512,6 +546,8 @@ def main():
         out["cylinder"] = cylinder_form(meshgen)
     if "original" in sections:
         out["original_scheme"] = original_scheme_form(sdugks, meshgen, sched)
+    if "cylinder200k" in sections:
+        out["cylinder200k"] = cylinder200k_form(sdugks, autotune, meshgen)
     if "large" in sections:
         out["large"] = large_form(sdugks, meshgen)
     if not a.no_cpu:

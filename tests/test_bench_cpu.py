@@ -46,7 +46,7 @@ def test_unknown_section_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--sections", "fp32dev,nope"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
-    assert set(_bench().SECTIONS) == {"fp32dev", "batch", "serving", "cylinder", "original", "large"}
+    assert set(_bench().SECTIONS) == {"fp32dev", "batch", "serving", "cylinder", "cylinder200k", "original", "large"}
 
 
 def test_malformed_schedule_is_refused():
