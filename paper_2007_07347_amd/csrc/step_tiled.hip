@@ -2,9 +2,11 @@
 // eleven-step summary) in one kernel: one workgroup per tile of cells, at
 // most one work item per thread in every phase.
 //
-//   phase 1  W, u and fbar+ = a f + b feq(W) (Eq. fbarplus) of the tile and
-//            its two halo rings, into LDS (halo values are recomputed by every
-//            tile that needs them instead of being stored to memory);
+//   phase 1  fbar+ = a f + b feq(W) (Eq. fbarplus) of the tile and its two
+//            halo rings into LDS, with the macros later phases read (rho and
+//            u of the tile and first ring, the momentum of the tile); halo
+//            values are recomputed by every tile that needs them instead of
+//            being stored to memory;
 //   phase 2  least-squares gradient of fbar+ (the LLSR normal equations solved
 //            through precomputed weights A^-1 d; boundary states are points at
 //            the face midpoints) for the tile and its first ring, into LDS (in
