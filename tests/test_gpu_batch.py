@@ -142,3 +142,41 @@ def test_batch_autotuner_times_every_candidate(sd, tmp_path):
     assert best == {"tile_cells": fastest["tile_cells"], "block_threads": fastest["block_threads"]}
     again, _ = autotune.autotune_batch(problems, candidates=cands, steps=5, cache=cache)
     assert again == best
+
+
+@pytest.mark.parametrize("sched", [(64, 256), (32, 128)])
+def test_full_size_64_cavity_batch(sd, oracle_mod, sched):
+    """The batched workload at its full size (64 tanh cavities, edges
+    log-uniform in [32, 512], Re uniform in [100, 5000], seed 2026, FP32
+    deviation storage, 2.29M cells) on the schedules the batch autotuner
+    chooses between: 30 batched steps give the same bits as each member
+    stepped alone, and the two smallest members, sampled against the FP64
+    oracle, stay within the FP32 deviation form's window bar."""
+    rng = np.random.default_rng(2026)
+    sizes = meshgen.log_uniform_int(rng, 32, 512, size=64)
+    res = rng.uniform(100.0, 5000.0, size=64)
+    tc, bt = sched
+    problems = [(meshgen.cavity(int(n), beta=1.5, U=0.1), dict(nu=0.1 / re, cfl=0.5)) for n, re in zip(sizes, res)]
+    assert sum(int(n) ** 2 for n in sizes) == 2289523
+    mk = lambda: [sd.Solver(m, b, precision=sd.FP32DEV, tile_cells=tc, block_threads=bt, **kw)
+                  for (m, b), kw in problems]
+    alone, batched = mk(), mk()
+    for s in alone:
+        s.step(30)
+    b = sd.Batch(batched)
+    b.step(30)
+    for k in range(64):
+        for x, y in zip(alone[k].state(), batched[k].state()):
+            assert np.array_equal(x, y), k
+    b.close()
+    for k in np.argsort(sizes, kind="stable")[:2]:
+        (m, bc), kw = problems[k]
+        o = oracle_mod.Oracle(m, bc, **kw)
+        o.step(30)
+        fg, Wg, _ = batched[k].state()
+        fo, Wo, _ = o.state()
+        ef = np.abs(fg - fo).max() / np.abs(fo).max()
+        ew = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+        assert ef <= 2e-6 and ew <= 2e-6, (k, ef, ew)
+    for s in alone + batched:
+        s.close()
