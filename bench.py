@@ -64,6 +64,8 @@ def parse():
     p.add_argument("--schedule", default="", metavar="T,B",
                    help="tile cells and threads per workgroup of the headline and FP32 forms instead of the "
                         "autotuner's pick (for counter runs, where the profiler distorts the autotuner's timings)")
+    p.add_argument("--batch-schedule", default="", metavar="T,B",
+                   help="schedule of every member of the batched form instead of the batch autotuner's pick")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     p.add_argument("--large-only", action="store_true",
@@ -172,7 +174,7 @@ def headline(sdugks, autotune, meshgen, a, precision):
     return s, mesh, bcs, kw, sched, nc, ms, wall, eps, kt
 
 
-def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
+def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200, schedule=""):
     """64 uneven cavities, batched (one launch per step, graph replay) against
     stepping each instance after the other."""
     import numpy as np
@@ -184,7 +186,11 @@ def batch_form(sdugks, autotune, meshgen, seed=2026, n_inst=64, steps=200):
                 for n, re in zip(sizes, res)]
     cells = int(sum(int(n) * int(n) for n in sizes))
     # one schedule for the whole batched launch, picked by timing the batch
-    sched, table = autotune.autotune_batch(problems)
+    if schedule:
+        t, bt = (int(x) for x in schedule.split(","))
+        sched, table = {"tile_cells": t, "block_threads": bt}, []
+    else:
+        sched, table = autotune.autotune_batch(problems)
     solvers = [sdugks.Solver(mesh, bcs, **sched, **kw) for mesh, bcs, kw in problems]
     b = sdugks.Batch(solvers)
     b.step(20)
@@ -479,9 +485,10 @@ def main():
     if unknown:
         print(f"unknown sections: {sorted(unknown)}; choose from {','.join(SECTIONS)}", file=sys.stderr)
         sys.exit(2)
-    if a.schedule and not (len(a.schedule.split(",")) == 2 and all(x.isdigit() for x in a.schedule.split(","))):
-        print(f"--schedule takes two integers T,B (got {a.schedule!r})", file=sys.stderr)
-        sys.exit(2)
+    for opt, v in (("--schedule", a.schedule), ("--batch-schedule", a.batch_schedule)):
+        if v and not (len(v.split(",")) == 2 and all(x.isdigit() for x in v.split(","))):
+            print(f"{opt} takes two integers T,B (got {v!r})", file=sys.stderr)
+            sys.exit(2)
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the multi-GPU design is described, not built.",
               file=sys.stderr)
@@ -537,7 +544,7 @@ def main():
         s32.close()
         progress("fp32 deviation form done")
     if "batch" in sections:
-        out["batch"] = batch_form(sdugks, autotune, meshgen)
+        out["batch"] = batch_form(sdugks, autotune, meshgen, schedule=a.batch_schedule)
         progress("batched form done")
     if "serving" in sections:
         out["serving"] = serving(meshgen)
