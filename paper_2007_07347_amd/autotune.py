@@ -69,6 +69,8 @@ def autotune(mesh, bcs, candidates=None, steps=200, cache=CACHE, refresh=False, 
             continue
         table.append({"tile_cells": t, "block_threads": b, "ms": ms})
     ok = [r for r in table if r["ms"] is not None]
+    if not ok:
+        raise RuntimeError("no candidate schedule fits: " + "; ".join(r["error"] for r in table))
     best = min(ok, key=lambda r: r["ms"])
     best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
     if cache:
@@ -131,6 +133,8 @@ def autotune_batch(problems, candidates=None, steps=50, cache=CACHE, refresh=Fal
             continue
         table.append({"tile_cells": t, "block_threads": b, "ms": ms})
     ok = [r for r in table if r["ms"] is not None]
+    if not ok:
+        raise RuntimeError("no candidate schedule fits: " + "; ".join(r["error"] for r in table))
     best = min(ok, key=lambda r: r["ms"])
     best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
     if cache:
