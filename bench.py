@@ -132,6 +132,19 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def paper_cylinder():
+    """The paper's own cylinder results from tests/golden/cylinder_present.txt:
+    ({Re: (Cd, L/R)} steady, {Re: (Cd, L/R, St)} unsteady)."""
+    steady, unsteady = {}, {}
+    with open(os.path.join(ROOT, "tests", "golden", "cylinder_present.txt")) as fh:
+        for line in fh:
+            f = line.split("#", 1)[0].split()
+            if f:
+                vals = tuple(float(v) for v in f[2:] if v != "-")
+                (steady if f[0] == "steady" else unsteady)[int(f[1])] = vals
+    return steady, unsteady
+
+
 def time_steps(step, n, stream=None):
     import torch
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -258,7 +271,7 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
     import math
     import numpy as np
     from paper_2007_07347_amd import cylinder, sdugks
-    paper = {10: (3.015, 0.493), 20: (2.115, 1.842), 40: (1.557, 4.490)}
+    paper, paper_u = paper_cylinder()
     mesh, bcs = meshgen.cylinder_ogrid(n_theta, n_r, seed=0)
     rows = []
     for re in (10, 20, 40):
@@ -274,7 +287,6 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
                      "paper_Cd": paper[re][0], "paper_L_over_R": paper[re][1]})
         s.close()
     unsteady = []
-    paper_u = {60: (1.4228, 0.1377), 80: (1.375, 0.1523), 100: (1.349, 0.1653)}
     for re in (60, 80, 100):
         t0 = time.perf_counter()
         s, r = cylinder.run_shedding(sdugks, mesh, bcs, re, t_transient=1500.0, t_sample=500.0, cfl=0.5, kick=0.2)
@@ -283,7 +295,7 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
         unsteady.append({"Re": re, "St": round(r["St"], 4), "Cd_mean": round(r["Cd_mean"], 4),
                          "Cl_amp": round(r["Cl_amp"], 4), "steps": r["steps"], "wall_s": round(time.perf_counter() - t0, 1),
                          "St_fit": round(-3.3265 / re + 0.1816 + 1.6e-4 * re, 4),
-                         "paper_Cd": paper_u[re][0], "paper_St": paper_u[re][1]})
+                         "paper_Cd": paper_u[re][0], "paper_St": paper_u[re][2]})
     return {"workload": f"circular cylinder, O-grid {n_theta}x{n_r} split into {2 * n_theta * n_r} triangles, "
                         f"r 0.5..20, u_inf 0.1, FP64; steady cases to residual {tol:g}, unsteady cases "
                         f"1500 time units of transient (transverse kick 0.2 u_inf in the near wake) then 500 sampled",

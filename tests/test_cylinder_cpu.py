@@ -28,3 +28,20 @@ def test_equilibrium_moments():
     ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1.0])
     assert np.allclose(f.sum(1), rho, atol=1e-15)
     assert np.allclose(f @ ex, rho * u, atol=1e-15) and np.allclose(f @ ey, rho * v, atol=1e-15)
+
+
+def test_golden_paper_cylinder_values():
+    """The transcribed paper values are consistent with what the paper says
+    of them: drag falls and the bubble grows with Re over the steady range, and
+    the Strouhal numbers follow the experimental fit it cites
+    (St = -3.3265/Re + 0.1816 + 1.6e-4 Re) to within 2 %."""
+    from conftest import read_cylinder_golden
+    g = read_cylinder_golden()
+    assert sorted(g["steady"]) == [10, 20, 40] and sorted(g["unsteady"]) == [60, 80, 100]
+    cd = [g["steady"][r][0] for r in (10, 20, 40)]
+    lr = [g["steady"][r][1] for r in (10, 20, 40)]
+    assert cd[0] > cd[1] > cd[2] and lr[0] < lr[1] < lr[2]
+    for re_, (cd_u, lr_u, st) in g["unsteady"].items():
+        fit = -3.3265 / re_ + 0.1816 + 1.6e-4 * re_
+        assert abs(st - fit) <= 0.02 * fit, (re_, st, fit)
+        assert cd_u < cd[2]
