@@ -39,6 +39,16 @@ def _load_cache(path):
         return {}
 
 
+def _store_cache(path, db):
+    """Best effort: a read-only location only costs the re-tuning."""
+    try:
+        with open(path + ".tmp", "w") as fh:
+            json.dump(db, fh, indent=1)
+        os.replace(path + ".tmp", path)
+    except OSError:
+        pass
+
+
 def time_candidate(mesh, bcs, tile_cells, block_threads, steps=200, warmup=20, **kw):
     import torch
     s = sdugks.Solver(mesh, bcs, tile_cells=tile_cells, block_threads=block_threads, **kw)
@@ -75,9 +85,7 @@ def autotune(mesh, bcs, candidates=None, steps=200, cache=CACHE, refresh=False, 
     best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
     if cache:
         db[key] = {"best": best, "table": table}
-        with open(cache + ".tmp", "w") as fh:
-            json.dump(db, fh, indent=1)
-        os.replace(cache + ".tmp", cache)
+        _store_cache(cache, db)
     return best, table
 
 
@@ -139,7 +147,5 @@ def autotune_batch(problems, candidates=None, steps=50, cache=CACHE, refresh=Fal
     best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
     if cache:
         db[key] = {"best": best, "table": table}
-        with open(cache + ".tmp", "w") as fh:
-            json.dump(db, fh, indent=1)
-        os.replace(cache + ".tmp", cache)
+        _store_cache(cache, db)
     return best, table
