@@ -175,3 +175,23 @@ def test_two_kernel_step_rejects_fp32dev(sd):
     with pytest.raises(sd.SdugksError) as ei:
         sd.Solver(*meshgen.hexagon_strip(4, 3), precision=sd.FP32DEV, nu=0.01)
     assert ei.value.code == sd.EINVAL
+
+
+def test_cavity_256_window_headline_schedule(sd, oracle_mod):
+    """The FP32 deviation headline at full size and in the bench's launch
+    shape (32-cell tiles, 128 threads): 60 steps from a generic state against
+    the FP64 oracle, within the window bar."""
+    mesh, bcs = meshgen.cavity(256)
+    kw = dict(nu=0.1 / 1000, cfl=0.5)
+    o = oracle_mod.Oracle(mesh, bcs, **kw)
+    g = sd.Solver(mesh, bcs, precision=sd.FP32DEV, tile_cells=32, block_threads=128, **kw)
+    f, W, _ = meshgen.random_state(o.n_cells, seed=29, amp=0.02)
+    o.set_state(f, W)
+    g.set_state(f, W)
+    o.step(60)
+    g.step(60)
+    fg, Wg, _ = g.state()
+    fo, Wo, _ = o.state()
+    ef, ew = rel_linf(fg, fo), rel_linf(Wg, Wo)
+    print("cavity256 fp32dev", f"f {ef:.2e} W {ew:.2e}", flush=True)
+    assert ef <= 2e-6 and ew <= 2e-6
