@@ -801,7 +801,9 @@ int batch_build(sdugks_batch_t *b)
         for (auto &g : want) {
             g.cap_inst = (int)next_pow2(g.n_inst);
             g.cap_tiles = (int)next_pow2(g.n_tiles);
-            g.lds = std::min(g.lds + g.lds / 4, kTileLdsLimit);    // headroom for later members
+            // LDS exactly the largest member's: a spare margin for later members
+            // would cost resident workgroups per CU on every step (a member that
+            // needs more rebuilds the group, like one that exceeds a capacity)
             if (hipMalloc((void **)&g.d_inst, g.cap_inst * sizeof(BatchInst)) != hipSuccess ||
                 hipMalloc((void **)&g.d_tmap, batch_grid(g.cap_tiles) * sizeof(int2)) != hipSuccess)
                 return fail(SDUGKS_ENOMEM, "hipMalloc of a batch table failed");
