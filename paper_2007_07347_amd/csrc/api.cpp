@@ -151,8 +151,10 @@ struct sdugks_batch_s {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipEvent_t ev = nullptr;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;       // one pair of steps
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_k = nullptr;     // kGraphPairs pairs of steps
+    hipGraphExec_t exec_k = nullptr;
     int device = 0;
     std::vector<int> cur_at_fill;     // members' buffer indices when the tables were filled
 };
@@ -758,8 +760,12 @@ void batch_release_graph(sdugks_batch_t *b)
 {
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec_k) hipGraphExecDestroy(b->exec_k);
+    if (b->graph_k) hipGraphDestroy(b->graph_k);
     b->exec = nullptr;
     b->graph = nullptr;
+    b->exec_k = nullptr;
+    b->graph_k = nullptr;
 }
 
 void batch_release_groups(sdugks_batch_t *b)
@@ -933,6 +939,30 @@ int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_
     return batch_build(b);
 }
 
+namespace {
+// Steps per replay of the long batch graph, in pairs (each pair returns every
+// member to its buffer parity).
+constexpr int64_t kGraphPairs = 16;
+
+// Capture `pairs` pairs of batched steps on the batch's stream into a graph.
+int batch_capture(sdugks_batch_t *b, int64_t pairs, hipGraph_t &graph, hipGraphExec_t &exec)
+{
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = 0;
+    for (int64_t k = 0; k < pairs && !rc; k++) {
+        rc = batch_launch(b, 0);
+        if (!rc) rc = batch_launch(b, 1);
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &gr);
+    if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
+    if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    graph = gr;
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    return SDUGKS_OK;
+}
+}  // namespace
+
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
 {
     if (!b) return fail(SDUGKS_EINVAL, "null batch");
@@ -950,18 +980,18 @@ int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
         }
     int rc = batch_join(b, true);
     if (rc) return rc;
+    // whole runs of kGraphPairs pairs replay the long graph (the gap the
+    // runtime leaves between two graph launches is then paid once per run),
+    // the remaining pairs the one-pair graph
     int64_t pairs = n / 2;
+    const int64_t runs = pairs / kGraphPairs;
+    pairs -= runs * kGraphPairs;
+    if (runs > 0) {
+        if (!b->exec_k && (rc = batch_capture(b, kGraphPairs, b->graph_k, b->exec_k))) return rc;
+        for (int64_t k = 0; k < runs; k++) HIPCHK(hipGraphLaunch(b->exec_k, b->stream));
+    }
     if (pairs > 0) {
-        if (!b->exec) {
-            HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            int r0 = batch_launch(b, 0), r1 = r0 ? r0 : batch_launch(b, 1);
-            hipGraph_t gr = nullptr;
-            hipError_t e = hipStreamEndCapture(b->stream, &gr);
-            if (r1) { if (gr) hipGraphDestroy(gr); return r1; }
-            if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-            b->graph = gr;
-            HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-        }
+        if (!b->exec && (rc = batch_capture(b, 1, b->graph, b->exec))) return rc;
         for (int64_t k = 0; k < pairs; k++) HIPCHK(hipGraphLaunch(b->exec, b->stream));
     }
     if (n & 1) {

@@ -502,17 +502,30 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
 template <int D, bool DEV>
 __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
 {
-    const int2 e = tab.tmap[xcd_tile((int)gridDim.x)];
-    if (e.x < 0) return;
-    const BatchInst &in = tab.inst[e.x];
-    const int p = in.parity0 ^ parity;
+    // the slot's (member, tile) as one 8-byte load, so that the tile index
+    // does not wait for the exit test on the member
+    const unsigned long long slot = reinterpret_cast<const unsigned long long *>(tab.tmap)[xcd_tile((int)gridDim.x)];
+    const int member = (int)(unsigned)slot, tile = (int)(unsigned)(slot >> 32);
+    // the member's record copied once: its fields are then requested together
+    // (no address depends on another field) and stay in scalar registers
+    // across the barriers instead of being reloaded from memory.  A slot past
+    // the live tiles (member -1) reads member 0's record and leaves; testing
+    // it only here keeps the record's address a single step after the slot.
+    const BatchInst &in = tab.inst[member < 0 ? 0 : member];
+    const DevMesh m = in.m;
+    const DevTiles tl = in.t;
+    const bool sw = ((in.parity0 ^ parity) & 1) != 0;
+    void *const f0 = in.f[0], *const f1 = in.f[1];
+    double *const W0 = in.W[0], *const W1 = in.W[1], *const G0 = in.G[0], *const G1 = in.G[1];
     DevState s;
-    s.W = in.W[p]; s.G = in.G[p]; s.Wo = in.W[p ^ 1]; s.Go = in.G[p ^ 1];
-    s.f = reinterpret_cast<const double *>(in.f[p]);
-    s.fo = reinterpret_cast<double *>(in.f[p ^ 1]);
-    s.f32 = reinterpret_cast<const float *>(in.f[p]);
-    s.fo32 = reinterpret_cast<float *>(in.f[p ^ 1]);
-    step_tile<D, DEV>(in.m, in.t, s, in.lagged, e.y);
+    s.W = sw ? W1 : W0; s.G = sw ? G1 : G0; s.Wo = sw ? W0 : W1; s.Go = sw ? G0 : G1;
+    void *const fi = sw ? f1 : f0, *const fo = sw ? f0 : f1;
+    s.f = reinterpret_cast<const double *>(fi);
+    s.fo = reinterpret_cast<double *>(fo);
+    s.f32 = reinterpret_cast<const float *>(fi);
+    s.fo32 = reinterpret_cast<float *>(fo);
+    if (member < 0) return;
+    step_tile<D, DEV>(m, tl, s, in.lagged, tile);
 }
 
 }  // namespace
