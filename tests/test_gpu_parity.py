@@ -272,3 +272,32 @@ def test_poison_is_detected_and_isolated(sd):
     f, W, _ = b.state()
     a.set_state(f, W)
     a.step(1)
+
+
+DEGENERATE = {
+    "cavity_1": lambda: meshgen.cavity(1),              # one cell, four boundary faces, no neighbour
+    "cavity_2": lambda: meshgen.cavity(2),              # every cell touches two walls
+    "couette_1x4": lambda: meshgen.couette(1, 4),       # each cell is its own periodic neighbour
+    "couette_2x2": lambda: meshgen.couette(2, 2),
+    "periodic_tri_1": lambda: meshgen.jittered_periodic_triangles(1, seed=2),   # two triangles, all faces glued
+}
+
+
+@pytest.mark.parametrize("precision", ["FP64", "FP32DEV"])
+@pytest.mark.parametrize("name", sorted(DEGENERATE))
+def test_degenerate_meshes(sd, oracle_mod, name, precision):
+    """Meshes at the edge of what the method allows: a single cell, cells with
+    more boundary faces than neighbours, a cell glued to itself through a
+    periodic pair, a two-triangle periodic square.  50 steps from a generic
+    state against the oracle, FP64 at the parity bar and the FP32 deviation
+    form within its window bar."""
+    mesh, bcs = DEGENERATE[name]()
+    kw = dict(nu=0.01, cfl=0.5)
+    o = oracle_mod.Oracle(mesh, bcs, **kw)
+    g = sd.Solver(mesh, bcs, precision=getattr(sd, precision), **kw)
+    f, W, _ = meshgen.random_state(o.n_cells, seed=31, amp=0.02)
+    o.set_state(f, W)
+    g.set_state(f, W)
+    o.step(50)
+    g.step(50)
+    compare(g, o, f"{name} {precision}", tol=TOL if precision == "FP64" else 2e-6)
