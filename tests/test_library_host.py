@@ -159,3 +159,10 @@ def test_symmetry_side_must_be_straight():
     b2[0] = meshgen.bc(meshgen.SYMMETRY)
     m2, b2 = meshgen.rotate(m2, b2, 0.4)
     sdugks.geometry(m2, b2, nu=0.01)
+
+
+def test_empty_mesh_is_rejected(lib):
+    import numpy as np
+    empty = {"node_xy": np.zeros((0, 2)), "cell_ptr": np.zeros(1, np.int32), "cell_nodes": np.zeros(0, np.int32),
+             "bedge_nodes": np.zeros((0, 2), np.int32), "bedge_tag": np.zeros(0, np.int32)}
+    _expect_einval(lib, empty, [meshgen.bc(meshgen.WALL)], "empty")
