@@ -64,6 +64,29 @@ __device__ __forceinline__ void static_for(F &&f)
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// Device-global memory, said so explicitly.  Pointers that the compiler
+// cannot trace to a kernel argument (a batched launch reads its members'
+// pointers from their records) would otherwise be accessed with flat
+// instructions, whose outstanding loads also hold up every wait on LDS and
+// scalar results.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+#else
+template <typename T>
+using gmem = T;   // the host pass only parses device code
+#endif
+template <typename T>
+__device__ __forceinline__ const gmem<T> *gin(const T *p)
+{
+    return (const gmem<T> *)p;
+}
+template <typename T>
+__device__ __forceinline__ gmem<T> *gout(T *p)
+{
+    return (gmem<T> *)p;
+}
+
 // c x for c in {-1, 0, 1}
 template <int C, typename T>
 __device__ __forceinline__ T cmul(T x)
@@ -223,16 +246,16 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // boundary-condition table [n_bc][4]: type, rho, u, v (16-byte aligned after the gradient)
     constexpr int SG = kGradStride;
     double *sbc = smem + (((3 * P1 + 2 * PT) * 8 + (9 * P + SG * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
-    const int16_t *ladj = tl.ladj + (size_t)t * D * P1;
-    const int16_t *lfc = tl.lfc + (size_t)t * D * PT;
+    const gmem<int16_t> *ladj = gin(tl.ladj + (size_t)t * D * P1);
+    const gmem<int16_t> *lfc = gin(tl.lfc + (size_t)t * D * PT);
     using R2 = typename std::conditional<DEV, float2, double2>::type;
-    const R2 *lw, *frt;
+    const gmem<R2> *lw, *frt;
     if constexpr (DEV) {
-        lw = tl.lw32 + (size_t)t * D * P1;
-        frt = tl.fr32 + (size_t)t * tl.nf_max * 3;
+        lw = gin(tl.lw32 + (size_t)t * D * P1);
+        frt = gin(tl.fr32 + (size_t)t * tl.nf_max * 3);
     } else {
-        lw = tl.lw + (size_t)t * D * P1;
-        frt = tl.fr + (size_t)t * tl.nf_max * 3;
+        lw = gin(tl.lw + (size_t)t * D * P1);
+        frt = gin(tl.fr + (size_t)t * tl.nf_max * 3);
     }
     const int PF = tl.nf_max;
     // fbar+ from the cell variable (phase 1); the face step: reconstruction
@@ -246,7 +269,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // padded entry is a valid filler (cell 0, no neighbour, zero weight, empty
     // face), so no request waits for the tile header, whose counts only mask
     // what lanes without work read.
-    const unsigned g1 = (unsigned)tl.lgid[(size_t)t * P + (tid < P ? tid : 0)];
+    const unsigned g1 = (unsigned)gin(tl.lgid)[(size_t)t * P + (tid < P ? tid : 0)];
     const int lc3 = tid >> 2, sl3 = tid & 3;
     const int sl3c = sl3 < D ? sl3 : D - 1;
     const int lc3c = lc3 < PT ? lc3 : 0;
@@ -271,19 +294,19 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     }
     const int a3 = ladj[sl3c * P1 + lc3c];
     const bool pb = tid < m.n_bc;
-    const DevBC bcl = m.bcs[pb ? tid : 0];
+    const DevBC bcl = gin(m.bcs)[pb ? tid : 0];
     __builtin_amdgcn_sched_barrier(0);
-    const double r = s.W[g1], mu = s.W[(size_t)np + g1], mv = s.W[2 * (size_t)np + g1];
+    const double r = gin(s.W)[g1], mu = gin(s.W)[(size_t)np + g1], mv = gin(s.W)[2 * (size_t)np + g1];
     R fv[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-        if constexpr (DEV) fv[i] = s.f32[(size_t)i * np + g1];
-        else fv[i] = s.f[(size_t)i * np + g1];
+        if constexpr (DEV) fv[i] = gin(s.f32)[(size_t)i * np + g1];
+        else fv[i] = gin(s.f)[(size_t)i * np + g1];
     }
     __builtin_amdgcn_sched_barrier(0);
     // the tile header: first cell and the counts of tile, first-ring and
     // second-ring cells, for the masks of each phase
-    const int *hd = tl.hdr + 8 * t;
+    const gmem<int> *hd = gin(tl.hdr + 8 * t);
     const int g0 = hd[0], nt = hd[1], na = nt + hd[2], nl = na + hd[3];
     const bool p1 = tid < nl, p2 = c2 < na, p3 = lc3 < nt;
 #pragma unroll
@@ -339,15 +362,15 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // (the tile's own cells, just read in phase 1: cache hits)
     double fo0, fo1, fo2;
     if constexpr (DEV) {
-        fo0 = s.f32[(size_t)sl3 * np + g3];
-        fo1 = s.f32[(size_t)(sl3 + 4) * np + g3];
-        fo2 = s.f32[(size_t)8 * np + g3];
+        fo0 = gin(s.f32)[(size_t)sl3 * np + g3];
+        fo1 = gin(s.f32)[(size_t)(sl3 + 4) * np + g3];
+        fo2 = gin(s.f32)[(size_t)8 * np + g3];
     } else {
-        fo0 = s.f[(size_t)sl3 * np + g3];
-        fo1 = s.f[(size_t)(sl3 + 4) * np + g3];
-        fo2 = s.f[(size_t)8 * np + g3];
+        fo0 = gin(s.f)[(size_t)sl3 * np + g3];
+        fo1 = gin(s.f)[(size_t)(sl3 + 4) * np + g3];
+        fo2 = gin(s.f)[(size_t)8 * np + g3];
     }
-    const double dtv = m.dtv[g3];
+    const double dtv = gin(m.dtv)[g3];
     R phi[9];
     double g0s = 0.0, g1s = 0.0, g2s = 0.0;
 #pragma unroll
@@ -423,17 +446,17 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     if (p3) {
         const int lc = lc3, g = g3;
         double G0 = g0s, G1 = g1s, G2 = g2s;
-        if (lagged) { G0 = s.G[g]; G1 = s.G[np + g]; G2 = s.G[2 * np + g]; }
+        if (lagged) { G0 = gin(s.G)[g]; G1 = gin(s.G)[np + g]; G2 = gin(s.G)[2 * np + g]; }
         const double rn = sW[lc] - dtv * G0;
         const double mxn = sM[lc] - dtv * G1;
         const double myn = sM[PT + lc] - dtv * G2;
-        if (sl3 == 0) s.Wo[g] = rn;
-        if (sl3 == 1) s.Wo[np + g] = mxn;
-        if (sl3 == 2) s.Wo[2 * np + g] = myn;
+        if (sl3 == 0) gout(s.Wo)[g] = rn;
+        if (sl3 == 1) gout(s.Wo)[np + g] = mxn;
+        if (sl3 == 2) gout(s.Wo)[2 * np + g] = myn;
         if (lagged) {
-            if (sl3 == 0) s.Go[g] = g0s;
-            if (sl3 == 1) s.Go[np + g] = g1s;
-            if (sl3 == 2) s.Go[2 * np + g] = g2s;
+            if (sl3 == 0) gout(s.Go)[g] = g0s;
+            if (sl3 == 1) gout(s.Go)[np + g] = g1s;
+            if (sl3 == 2) gout(s.Go)[2 * np + g] = g2s;
         }
         const double irn = 1.0 / rn;
         const double un = mxn * irn, vn = myn * irn, uun = un * un + vn * vn;
@@ -458,8 +481,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             v0 = (4.0 / 3.0) * (double)sfbp[lc * 9 + i0] - (1.0 / 3.0) * fo0 - dtv * F0;
             v1 = (4.0 / 3.0) * (double)sfbp[lc * 9 + i1] - (1.0 / 3.0) * fo1 - dtv * F1;
         }
-        if constexpr (DEV) { s.fo32[(size_t)i0 * np + g] = (float)v0; s.fo32[(size_t)i1 * np + g] = (float)v1; }
-        else { s.fo[(size_t)i0 * np + g] = v0; s.fo[(size_t)i1 * np + g] = v1; }
+        if constexpr (DEV) { gout(s.fo32)[(size_t)i0 * np + g] = (float)v0; gout(s.fo32)[(size_t)i1 * np + g] = (float)v1; }
+        else { gout(s.fo)[(size_t)i0 * np + g] = v0; gout(s.fo)[(size_t)i1 * np + g] = v1; }
         if (sl3 == 0) {
             double v2;
             if (m.scheme == 0) {
@@ -468,8 +491,8 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             } else {
                 v2 = (4.0 / 3.0) * (double)sfbp[lc * 9 + 8] - (1.0 / 3.0) * fo2 - dtv * (double)phi[8];
             }
-            if constexpr (DEV) s.fo32[(size_t)8 * np + g] = (float)v2;
-            else s.fo[(size_t)8 * np + g] = v2;
+            if constexpr (DEV) gout(s.fo32)[(size_t)8 * np + g] = (float)v2;
+            else gout(s.fo)[(size_t)8 * np + g] = v2;
         }
     }
 }
