@@ -202,10 +202,11 @@ const char *sdugks_last_error(void);
  * all members; members with three-slot and four-slot cells, or with the two
  * storage forms, go to separate launches.  Each XCD takes an equal,
  * contiguous share of the concatenated tile sequence.  Steps are replayed
- * from a captured two-step hipGraph that reads a device-side table (members,
- * and each tile slot's member and local tile), so changing the membership
- * only rewrites the table unless the tile count outgrows the launch capacity
- * (it is then re-captured).
+ * from captured hipGraphs (one of 32 steps, one of 2 for the rest) that read
+ * a device-side table (members, and each tile slot's member and local tile),
+ * so changing the membership only rewrites the table unless the tile count
+ * or the LDS a member needs outgrows what the launch was captured with (it is
+ * then re-captured).
  *  - members: handles using the fused step (n >= 1, no duplicates, same
  *    device); they keep their own state and stay usable individually, and the
  *    batch does not own them: destroy the batch (or change its membership)
