@@ -521,7 +521,10 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
 // a fixed capacity and each block reads its member and local tile from the
 // device map (one load; member -1 past the live tiles), so the table can
 // change between launches of a captured graph.  parity selects each
-// instance's ping-pong buffers: it reads buffer (parity0 ^ parity).
+// instance's ping-pong buffers: it reads buffer (parity0 ^ parity).  Global
+// memory is reached through global-address-space pointers (gin, gout in
+// step_tile): the members' pointers come from their records, not from
+// kernel arguments.
 template <int D, bool DEV>
 __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
 {
@@ -532,8 +535,8 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
     // the member's record copied once: its fields are then requested together
     // (no address depends on another field) and stay in scalar registers
     // across the barriers instead of being reloaded from memory.  A slot past
-    // the live tiles (member -1) reads member 0's record and leaves; testing
-    // it only here keeps the record's address a single step after the slot.
+    // the live tiles (member -1) leaves without stepping (the compiler may
+    // take that exit before the record is requested).
     const BatchInst &in = tab.inst[member < 0 ? 0 : member];
     const DevMesh m = in.m;
     const DevTiles tl = in.t;
