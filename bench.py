@@ -13,15 +13,17 @@ instances one after another; the continuous-batching serving loop on a finite
 seeded request trace with p50/p99 time-to-steady, against the per-case FP64
 loop; steady drag, lift, stagnation pressure and recirculation length of the
 circular cylinder at Re = 10, 20, 40 and its Strouhal number and mean drag at
-Re = 60, 80, 100; the original half-step DUGKS against the simplified
-scheme (cost per step on the headline cavity, shear-wave accuracy, largest
-stable CFL against Dt/tau); the share of the HBM peak on a 2048 x 2048 cavity
-whose working set is far beyond the Infinity Cache; the HBM roofline of the
-step kernel; and the CPU oracle timed on a bounded sample of the headline
-workload.
+Re = 60, 80, 100; throughput on the 200,000-triangle cylinder O-grid in both
+storage forms; the original half-step DUGKS against the simplified scheme
+(cost per step on the headline cavity, shear-wave accuracy, largest stable
+CFL against Dt/tau); the share of the HBM peak on a 2048 x 2048 cavity whose
+working set is far beyond the Infinity Cache; the HBM roofline of the step
+kernel; and the CPU oracle timed on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra | --sections a,b,...]
-    python bench.py --copy-calibration MB     (plain device copy, for counter scaling)
+                    [--schedule T,B] [--batch-schedule T,B]
+    python bench.py --copy-calibration MB     (plain device copy, for counter scaling, and copy,
+                                               read and write bandwidth)
     python bench.py --large-only              (only the 2048 x 2048 cavity, for HBM counters)
 """
 from __future__ import annotations
