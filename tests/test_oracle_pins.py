@@ -278,6 +278,34 @@ def test_mirror_symmetry(oracle_mod):
     assert np.abs(u1).max() > 1e-3          # the flow is not trivially zero
 
 
+def test_quarter_turn_symmetry(oracle_mod):
+    """The cavity turned a quarter turn about the origin, with the lid velocity
+    turned alike, gives the turned flow: (u, v) -> (-v, u) in every cell.  The
+    D2Q9 set maps onto itself under the turn, so a mix-up of the x and y
+    lattice components anywhere (a transposed operand, a swapped row) breaks
+    this while the mirror test above still holds."""
+    n = 10
+    mesh, bcs = meshgen.cavity(n)
+    # the turn done exactly, (x, y) -> (-y, x): a turn through cos and sin
+    # leaves faces tilted by 1e-17, and velocities that lie exactly along a
+    # face (the averaged upwind tie) would then pick one side
+    rm = dict(mesh)
+    rm["node_xy"] = np.ascontiguousarray(np.stack([-mesh["node_xy"][:, 1], mesh["node_xy"][:, 0]], axis=1))
+    rb = [meshgen.bc(meshgen.WALL), meshgen.bc(meshgen.WALL, u=0.0, v=0.1)]
+    o1 = oracle_mod.Oracle(mesh, bcs, nu=0.002, cfl=0.5)
+    o2 = oracle_mod.Oracle(rm, rb, nu=0.002, cfl=0.5)
+    assert o2.dt == pytest.approx(o1.dt, rel=1e-14)
+    o1.step(300)
+    o2.step(300)
+    r1, u1, v1 = o1.macros()
+    r2, u2, v2 = o2.macros()
+    # rotate keeps cell ids: cell c of the turned mesh is the image of cell c
+    assert np.abs(r1 - r2).max() <= 1e-13
+    assert np.abs(u2 + v1).max() <= 1e-13
+    assert np.abs(v2 - u1).max() <= 1e-13
+    assert np.abs(v1).max() > 1e-3          # both components are exercised
+
+
 # --------------------------------------------------------------- physics
 @pytest.mark.parametrize("ny", [8, 16])
 def test_couette_steady_profile_is_linear(oracle_mod, ny):
