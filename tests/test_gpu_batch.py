@@ -84,9 +84,12 @@ def test_graph_replays_with_eager_work_between(sd):
     b.close()
 
 
-def test_continuous_batching_membership_changes(sd):
-    """Members join and leave between steps (admission / retirement): results
-    stay bitwise those of stepping each instance alone."""
+@pytest.mark.parametrize("steps", [5, 37])
+def test_continuous_batching_membership_changes(sd, steps):
+    """Members join and leave between steps (admission / retirement; members
+    that need more LDS than the launch was captured with force a rebuild):
+    results stay bitwise those of stepping each instance alone, both with
+    short runs and with runs long enough to replay the long graph."""
     specs = members(sd)
     alone = make(sd, specs, seed=300)
     batched = make(sd, members(sd), seed=300)
@@ -94,9 +97,9 @@ def test_continuous_batching_membership_changes(sd):
     plan = [[0, 1], [0, 1, 2, 3], [1, 3, 4], [0, 1, 2, 3, 4, 5], [5], [2, 4]]
     for ids in plan:
         b.set_members([batched[k] for k in ids])
-        b.step(5)
+        b.step(steps)
         for k in ids:
-            alone[k].step(5)
+            alone[k].step(steps)
     assert_same(states(alone), states(batched))
     b.close()
 
