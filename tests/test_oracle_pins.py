@@ -512,6 +512,31 @@ def test_symmetry_uniform_parallel_flow_is_fixed_point(oracle_mod):
     assert np.abs(f - f0).max() <= 1e-14
 
 
+def test_inlet_outlet_uniform_flow_is_fixed_point(oracle_mod):
+    """A channel with an inlet at (rho0, U), an outlet and free-slip sides,
+    started from the uniform equilibrium of the inlet state, stays there: the
+    inlet supplies that state, the outlet carries the inner state out and the
+    sides reflect a normal velocity that is zero.  A wrong sign or index in
+    either open boundary breaks it."""
+    mesh = meshgen.structured(np.linspace(0.0, 1.0, 9), meshgen.tanh_nodes(6, 1.0), tag_bottom=3, tag_right=1,
+                              tag_top=4, tag_left=2)
+    U = 0.06
+    bcs = [meshgen.bc(meshgen.WALL), meshgen.bc(meshgen.OUTLET), meshgen.bc(meshgen.INLET, rho=1.0, u=U, v=0.0),
+           meshgen.bc(meshgen.SYMMETRY), meshgen.bc(meshgen.SYMMETRY)]
+    o = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
+    n = o.n_cells
+    f0 = np.tile(oracle_mod.feq(1.0, U, 0.0), (n, 1))
+    o.set_state(f0, np.tile([1.0, U, 0.0], (n, 1)))
+    o.step(300)
+    f, W, _ = o.state()
+    assert np.abs(f - f0).max() <= 1e-14
+    # the same channel started at rest is driven towards the inlet velocity
+    o2 = oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5)
+    o2.step(300)
+    _, u, _ = o2.macros()
+    assert u.min() > 0.0
+
+
 def test_symmetry_couette_free_slip_moves_with_the_wall(oracle_mod):
     """A moving wall over a free-slip (symmetry) plane drags the whole layer
     to its own velocity: the steady state is u = U everywhere, with no shear
