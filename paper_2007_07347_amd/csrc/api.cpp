@@ -811,8 +811,18 @@ int batch_build(sdugks_batch_t *b)
             // would cost resident workgroups per CU on every step (a member that
             // needs more rebuilds the group, like one that exceeds a capacity)
             if (hipMalloc((void **)&g.d_inst, g.cap_inst * sizeof(BatchInst)) != hipSuccess ||
-                hipMalloc((void **)&g.d_tmap, batch_grid(g.cap_tiles) * sizeof(int2)) != hipSuccess)
+                hipMalloc((void **)&g.d_tmap, batch_grid(g.cap_tiles) * sizeof(int2)) != hipSuccess) {
+                // free what this rebuild allocated and leave the batch empty:
+                // with no tables a later step would flip the members' buffer
+                // index without advancing them
+                for (auto &x : want) {
+                    if (x.d_inst) hipFree(x.d_inst);
+                    if (x.d_tmap) hipFree(x.d_tmap);
+                }
+                b->members.clear();
+                b->cur_at_fill.clear();
                 return fail(SDUGKS_ENOMEM, "hipMalloc of a batch table failed");
+            }
         }
         b->groups = want;
         for (auto &g : want) g.d_inst = nullptr, g.d_tmap = nullptr;
@@ -957,8 +967,13 @@ int batch_capture(sdugks_batch_t *b, int64_t pairs, hipGraph_t &graph, hipGraphE
     hipError_t e = hipStreamEndCapture(b->stream, &gr);
     if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
     if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        hipGraphDestroy(gr);
+        exec = nullptr;
+        return fail(SDUGKS_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ie));
+    }
     graph = gr;
-    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
     return SDUGKS_OK;
 }
 }  // namespace
