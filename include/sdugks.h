@@ -218,9 +218,10 @@ const char *sdugks_last_error(void);
 typedef struct sdugks_batch_s sdugks_batch_t;
 int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugks_batch_t **out);
 /* Replace the membership (continuous batching): waits for the batch stream.
- * If the device tables cannot be allocated (SDUGKS_ENOMEM) the batch is left
- * with no members: stepping it then advances nothing until members are set
- * again. */
+ * If the new members pass the checks but the device tables cannot be
+ * allocated (SDUGKS_ENOMEM) or filled (SDUGKS_EHIP), the batch is left with
+ * no members: stepping it then advances nothing until members are set again.
+ * The same holds for the table refresh inside sdugks_batch_step. */
 int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_t n);
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n);
 int sdugks_batch_destroy(sdugks_batch_t *b);

@@ -780,7 +780,7 @@ void batch_release_groups(sdugks_batch_t *b)
 // (Re)build the device tables for the current members.  Existing tables and
 // the captured graph are kept when every group still fits their capacity,
 // launch shape and LDS; otherwise they are reallocated and the graph dropped.
-int batch_build(sdugks_batch_t *b)
+int batch_build_tables(sdugks_batch_t *b)
 {
     std::vector<BatchGroup> want;
     for (size_t k = 0; k < b->members.size(); k++) {
@@ -812,15 +812,10 @@ int batch_build(sdugks_batch_t *b)
             // needs more rebuilds the group, like one that exceeds a capacity)
             if (hipMalloc((void **)&g.d_inst, g.cap_inst * sizeof(BatchInst)) != hipSuccess ||
                 hipMalloc((void **)&g.d_tmap, batch_grid(g.cap_tiles) * sizeof(int2)) != hipSuccess) {
-                // free what this rebuild allocated and leave the batch empty:
-                // with no tables a later step would flip the members' buffer
-                // index without advancing them
                 for (auto &x : want) {
                     if (x.d_inst) hipFree(x.d_inst);
                     if (x.d_tmap) hipFree(x.d_tmap);
                 }
-                b->members.clear();
-                b->cur_at_fill.clear();
                 return fail(SDUGKS_ENOMEM, "hipMalloc of a batch table failed");
             }
         }
@@ -867,6 +862,21 @@ int batch_build(sdugks_batch_t *b)
         HIPCHK(hipStreamSynchronize(b->stream));
     }
     return SDUGKS_OK;
+}
+
+// batch_build_tables, and on any failure a batch with no members, tables or
+// graphs: tables left half filled (or a step with none, which would flip the
+// members' buffer index without advancing them) must never be launched
+int batch_build(sdugks_batch_t *b)
+{
+    const int rc = batch_build_tables(b);
+    if (rc) {
+        batch_release_graph(b);
+        batch_release_groups(b);
+        b->members.clear();
+        b->cur_at_fill.clear();
+    }
+    return rc;
 }
 
 int batch_launch(sdugks_batch_t *b, int parity)
