@@ -644,8 +644,12 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
     HIPCHK(hipSetDevice(h->device));
     const bool tiled = h->mb.n_tiles > 0;
     const int nk = tiled ? 1 : 2;
-    hipEvent_t ev[3];
-    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    struct Events {                       // destroyed on every return path
+        hipEvent_t e[3] = {nullptr, nullptr, nullptr};
+        ~Events() { for (hipEvent_t x : e) if (x) hipEventDestroy(x); }
+    } evs;
+    hipEvent_t *ev = evs.e;
+    for (int k = 0; k < 3; k++) HIPCHK(hipEventCreate(&ev[k]));
     double acc[2] = {0, 0};
     for (int64_t k = 0; k < n; k++) {
         DevState s = h->state();
@@ -669,7 +673,6 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
         h->cur ^= 1;
         h->step++;
     }
-    for (auto &e : ev) hipEventDestroy(e);
     for (int k = 0; k < nk; k++) avg_ms[k] = n ? acc[k] / n : 0;
     if (names) {
         if (tiled) names[0] = "k_step_tiled";
