@@ -60,3 +60,32 @@ def test_every_schedule_gives_the_same_bits(sd, name, precision):
             continue
         for a, b in zip(st, ref):
             assert np.array_equal(a, b), (name, precision, tc, bt)
+
+
+@pytest.mark.parametrize("case", ["cavity_40_fp64", "cavity_40_fp32dev", "hexagons"])
+def test_profiled_step_equals_step(sd, case):
+    """The profiled step (an event pair around every launch, used by the bench
+    for per-kernel times) advances the state bit for bit like the plain step,
+    counts its steps, and names the kernels it timed."""
+    if case == "hexagons":
+        mesh, bcs = meshgen.hexagon_strip(6, 5)
+        kw, names = dict(nu=1e-2), ["k_grad", "k_flux_update"]
+    else:
+        mesh, bcs = meshgen.cavity(40)
+        kw = dict(nu=1e-3, precision=sd.FP32DEV if case.endswith("fp32dev") else sd.FP64)
+        names = ["k_step_tiled"]
+    a, b = sd.Solver(mesh, bcs, **kw), sd.Solver(mesh, bcs, **kw)
+    f, W, _ = meshgen.random_state(a.n_cells, seed=11, amp=0.01)
+    a.set_state(f, W)
+    b.set_state(f, W)
+    a.step(7)
+    kt = b.step_profiled(7)
+    assert list(kt) == names and all(v > 0 for v in kt.values()), kt
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    a.step(3)
+    b.step(3)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    a.close()
+    b.close()
