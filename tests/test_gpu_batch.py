@@ -183,3 +183,35 @@ def test_full_size_64_cavity_batch(sd, oracle_mod, sched):
         assert ef <= 2e-6 and ew <= 2e-6, (k, ef, ew)
     for s in alone + batched:
         s.close()
+
+
+def test_members_on_their_own_streams(sd):
+    """Members enqueue on streams of their own and the batch on another: the
+    batch waits for work each member queued before it, and each member's
+    later work waits for the batch, so the interleaving gives the same bits
+    as stepping every instance alone on one stream."""
+    import torch
+    specs = members(sd)[:4]
+    alone = make(sd, members(sd)[:4], seed=400)
+    streams = [torch.cuda.Stream() for _ in specs]
+    batched = []
+    for k, ((mesh, bcs), kw) in enumerate(specs):
+        kw = dict(kw)
+        s = sd.Solver(mesh, bcs, stream=streams[k], cfl=kw.pop("cfl", 0.5), **kw)
+        f, W, _ = meshgen.random_state(s.n_cells, seed=400 + k, amp=0.01)
+        s.set_state(f, W)
+        batched.append(s)
+    b = sd.Batch(batched, stream=torch.cuda.Stream())
+    for rnd in range(4):
+        for k, s in enumerate(batched):       # queued, not waited for
+            s.step(k + 1)
+        b.step(5 + rnd)
+        for s in batched[::2]:
+            s.step(2)
+        for k, s in enumerate(alone):
+            s.step(k + 1)
+            s.step(5 + rnd)
+        for s in alone[::2]:
+            s.step(2)
+    assert_same(states(alone), states(batched))
+    b.close()
