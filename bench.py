@@ -21,7 +21,7 @@ working set is far beyond the Infinity Cache; the HBM roofline of the step
 kernel; and the CPU oracle timed on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra | --sections a,b,...]
-                    [--schedule T,B] [--batch-schedule T,B]
+                    [--schedule T,B] [--batch-schedule T,B] [--cylinder-schedule T,B]
     python bench.py --copy-calibration MB     (plain device copy, for counter scaling, and copy,
                                                read and write bandwidth)
     python bench.py --large-only              (only the 2048 x 2048 cavity, for HBM counters)
@@ -68,6 +68,9 @@ def parse():
                         "autotuner's pick (for counter runs, where the profiler distorts the autotuner's timings)")
     p.add_argument("--batch-schedule", default="", metavar="T,B",
                    help="schedule of every member of the batched form instead of the batch autotuner's pick")
+    p.add_argument("--cylinder-schedule", default="", metavar="T,B",
+                   help="schedule of both precisions on the 200,000-triangle cylinder instead of the autotuner's "
+                        "picks (for profiled runs)")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-calibration", type=int, default=0, metavar="MB")
     p.add_argument("--large-only", action="store_true",
@@ -414,11 +417,11 @@ def original_scheme_form(sdugks, meshgen, sched, steps=3000):
                           "dt_over_tau": list(ratios), "rows": stability}}
 
 
-def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50):
+def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50, schedule=""):
     """Throughput on the 200,000-triangle cylinder O-grid (Re 40, far-field
     inflow 0.1) in FP32 deviation storage and in FP64, each on its autotuned
-    schedule, and the FP32 form's velocity deviation from FP64 after the
-    same steps from rest."""
+    schedule (or both on the given "T,B"), and the FP32 form's velocity
+    deviation from FP64 after the same steps from rest."""
     import numpy as np
     import torch
     mesh, bcs = meshgen.cylinder_ogrid(400, 250, seed=0)
@@ -427,7 +430,11 @@ def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50):
     uv = {}
     for prec, pname in ((sdugks.FP32DEV, "fp32dev"), (sdugks.FP64, "f64")):
         kw = dict(nu=0.1 / 40, cfl=0.5, u0=0.1, precision=prec)
-        sched, _ = autotune.autotune(mesh, bcs, steps=100, **kw)
+        if schedule:
+            t, b = (int(x) for x in schedule.split(","))
+            sched = {"tile_cells": t, "block_threads": b}
+        else:
+            sched, _ = autotune.autotune(mesh, bcs, steps=100, **kw)
         s = sdugks.Solver(mesh, bcs, **sched, **kw)
         s.step(warmup)
         torch.cuda.synchronize()
@@ -499,7 +506,8 @@ def main():
     if unknown:
         print(f"unknown sections: {sorted(unknown)}; choose from {','.join(SECTIONS)}", file=sys.stderr)
         sys.exit(2)
-    for opt, v in (("--schedule", a.schedule), ("--batch-schedule", a.batch_schedule)):
+    for opt, v in (("--schedule", a.schedule), ("--batch-schedule", a.batch_schedule),
+                   ("--cylinder-schedule", a.cylinder_schedule)):
         if v and not (len(v.split(",")) == 2 and all(x.isdigit() for x in v.split(","))):
             print(f"{opt} takes two integers T,B (got {v!r})", file=sys.stderr)
             sys.exit(2)
@@ -568,7 +576,7 @@ def main():
     if "original" in sections:
         out["original_scheme"] = original_scheme_form(sdugks, meshgen, sched)
     if "cylinder200k" in sections:
-        out["cylinder200k"] = cylinder200k_form(sdugks, autotune, meshgen)
+        out["cylinder200k"] = cylinder200k_form(sdugks, autotune, meshgen, schedule=a.cylinder_schedule)
     if "large" in sections:
         out["large"] = large_form(sdugks, meshgen)
     if not a.no_cpu:

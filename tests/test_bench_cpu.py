@@ -7,6 +7,8 @@ import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -49,10 +51,11 @@ def test_unknown_section_is_refused():
     assert set(_bench().SECTIONS) == {"fp32dev", "batch", "serving", "cylinder", "cylinder200k", "original", "large"}
 
 
-def test_malformed_schedule_is_refused():
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--schedule", "32"],
+@pytest.mark.parametrize("opt", ["--schedule", "--batch-schedule", "--cylinder-schedule"])
+def test_malformed_schedule_is_refused(opt):
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), opt, "32"],
                        capture_output=True, text=True, timeout=120)
-    assert r.returncode == 2 and "--schedule takes two integers" in r.stderr
+    assert r.returncode == 2 and f"{opt} takes two integers" in r.stderr
 
 
 def test_traffic_requires_the_recorded_schedule(tmp_path, monkeypatch):
