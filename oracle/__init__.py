@@ -25,12 +25,13 @@ _lib = None
 
 
 def build(force=True):
-    """Compile the oracle with gcc (-O2, no contraction, no fast-math)."""
+    """Compile the oracle with gcc (-O2, no contraction, no fast-math, OpenMP
+    over cells and faces; one thread unless set_threads says otherwise)."""
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
         return LIB
     tmp = LIB + ".tmp"
     subprocess.run(["gcc", "-std=c99", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                    "-Wall", "-Wno-unused-result", SRC, "-o", tmp, "-lm"], check=True)
+                    "-fopenmp", "-Wall", "-Wno-unused-result", SRC, "-o", tmp, "-lm"], check=True)
     os.replace(tmp, LIB)
     return LIB
 
@@ -58,9 +59,20 @@ def _load():
     lib.orc_mass.restype = C.c_double
     lib.orc_feq.argtypes = [C.c_double, C.c_double, C.c_double, P]
     lib.orc_lsq_gradient.argtypes = [P, P, P, P, C.c_int]
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_max_threads.restype = C.c_int
+    lib.orc_set_threads(1)
     lib.orc_face_states.argtypes = [P, P, P, P]
     _lib = lib
     return lib
+
+
+def set_threads(n):
+    """Threads of the oracle's per-cell and per-face loops (results do not
+    depend on it); returns the count in effect."""
+    lib = _load()
+    lib.orc_set_threads(int(n))
+    return int(lib.orc_max_threads())
 
 
 def _p(a):

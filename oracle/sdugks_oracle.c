@@ -77,6 +77,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* D2Q9 lattice: rest, four axis velocities, four diagonals (c = 1). */
 static const int EX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -524,11 +527,13 @@ void orc_lsq_gradient(const orc_case *o, const double *field, const double *bfie
 /* steps 2 and 3: fbar+ at every centre, the boundary states, the gradients */
 static void prepare(orc_case *o, int cramer)
 {
-    double fe[9];
+    #pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; c++) {
+        double fe[9];
         feq_of_W(&o->W[3 * c], fe);
         for (int i = 0; i < 9; i++) o->fbp[9 * c + i] = o->a * o->f[9 * c + i] + o->b * fe[i];
     }
+    #pragma omp parallel for schedule(static)
     for (int f = 0; f < o->nf; f++) {
         if (o->fn[f] >= 0) continue;
         int c = o->fo[f], t = o->fbc[f];
@@ -552,6 +557,7 @@ static void prepare(orc_case *o, int cramer)
             o->ghost[9 * f + i] = o->a * fb + o->b * feb[i];            /* its fbar+ */
         }
     }
+    #pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; c++)
         for (int i = 0; i < 9; i++) {
             if (cramer) lsq_cramer(o, o->fbp, o->ghost, 9, i, c, &o->sig[18 * c + 2 * i], &o->sig[18 * c + 2 * i + 1]);
@@ -611,8 +617,11 @@ static void one_step(orc_case *o)
 {
     int brute = (o->assembly == ORC_BRUTE);
     prepare(o, brute);
-    double fb[9], ff[9];
-    for (int f = 0; f < o->nf; f++) face_flux(o, f, fb, ff, &o->phi[9 * f], &o->gam[3 * f]);
+    #pragma omp parallel for schedule(static)
+    for (int f = 0; f < o->nf; f++) {
+        double fb[9], ff[9];
+        face_flux(o, f, fb, ff, &o->phi[9 * f], &o->gam[3 * f]);
+    }
     if (brute) {
         /* scatter in face order */
         memset(o->F, 0, sizeof(double) * 9 * o->nc);
@@ -628,6 +637,7 @@ static void one_step(orc_case *o)
         }
     } else {
         /* gather in each cell's polygon edge order */
+        #pragma omp parallel for schedule(static)
         for (int c = 0; c < o->nc; c++) {
             double Fc[9] = {0}, Gc[3] = {0};
             for (int q = o->cf_ptr[c]; q < o->cf_ptr[c + 1]; q++) {
@@ -642,8 +652,9 @@ static void one_step(orc_case *o)
         }
     }
     /* steps 9-11 */
-    double fe[9];
+    #pragma omp parallel for schedule(static)
     for (int c = 0; c < o->nc; c++) {
+        double fe[9];
         double k = o->dt / o->area[c];
         const double *Gs = (o->macro_mode == ORC_LAGGED) ? &o->G[3 * c] : &o->Gn[3 * c];
         for (int m = 0; m < 3; m++) o->W[3 * c + m] = o->W[3 * c + m] - k * Gs[m];
@@ -659,6 +670,28 @@ static void one_step(orc_case *o)
             o->f[9 * c + i] = (o->f[9 * c + i] - k * o->F[9 * c + i] + o->lam * fe[i]) / (1.0 + o->lam);
         for (int m = 0; m < 3; m++) o->G[3 * c + m] = o->Gn[3 * c + m];
     }
+}
+
+/* Threads of the per-cell and per-face loops (OpenMP when compiled with it):
+ * every iteration computes the same operations on the same operands whatever
+ * thread runs it, so the results do not depend on the thread count.  The
+ * scatter of the brute-force assembly stays serial, in face order. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void orc_step(orc_case *o, int n)

@@ -51,6 +51,9 @@ void orc_faces(const orc_case *o, int *owner, int *nbr, int *bcid, double *lnx, 
 void orc_set_state(orc_case *o, const double *f, const double *W, const double *G);
 void orc_get_state(const orc_case *o, double *f, double *W, double *G);
 void orc_step(orc_case *o, int n);
+/* threads of the per-cell / per-face loops (results independent of it) */
+void orc_set_threads(int n);
+int orc_max_threads(void);
 /* relative L2 change of (U, V) since the last call (or creation), then re-snapshot */
 double orc_residual(orc_case *o);
 double orc_mass(const orc_case *o);

@@ -629,3 +629,26 @@ def test_original_scheme_has_no_lagged_flux(oracle_mod):
     mesh, bcs = meshgen.cavity(4)
     with pytest.raises(ValueError):
         oracle_mod.Oracle(mesh, bcs, nu=0.01, cfl=0.5, scheme=1, macro=0)
+
+
+# ---------------------------------------------------------------- threads
+@pytest.mark.parametrize("assembly", [0, 1])
+def test_oracle_threads_do_not_change_results(oracle_mod, assembly):
+    """The oracle's per-cell and per-face loops run on several threads for the
+    CPU baseline: every cell and face is computed by the same operations on
+    the same operands whatever thread takes it, so 1 and N threads give
+    identical bits (cavity with a lid and a periodic jittered triangle mesh,
+    from a generic state)."""
+    for mesh, bcs, kw in ((*meshgen.cavity(19), dict(nu=1e-3, cfl=0.5)),
+                          (*meshgen.jittered_periodic_triangles(9, seed=2), dict(nu=4e-3, cfl=0.5))):
+        out = []
+        for threads in (1, 4):
+            assert oracle_mod.set_threads(threads) == threads
+            o = oracle_mod.Oracle(mesh, bcs, assembly=assembly, **kw)
+            f, W, G = meshgen.random_state(o.n_cells, seed=11, amp=0.03)
+            o.set_state(f, W, 0 * G)
+            o.step(25)
+            out.append(o.state())
+        oracle_mod.set_threads(1)
+        for a, b in zip(*out):
+            assert np.array_equal(a, b)
