@@ -146,8 +146,16 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
                   void *stream, void *workspace, size_t workspace_bytes, sdugks_t **out);
 
 /* Advance n >= 0 time steps (asynchronous).  Fails with SDUGKS_EDIVERGED once a
- * residual, mass or state call has seen a non-finite value. */
+ * residual, mass or state call has seen a non-finite value.  Pairs of steps
+ * are replayed from hipGraphs captured on first use (32 steps per replay, then
+ * 2; an odd last step is launched alone); the graphs are captured on a private
+ * stream of the handle and launched on its stream, which may be the null
+ * stream.  Results are bitwise those of sdugks_step_eager. */
 int sdugks_step(sdugks_t *h, int64_t n);
+
+/* The same n steps with one plain kernel launch each (no graph): for callers
+ * that capture their own graph around the library, or time single launches. */
+int sdugks_step_eager(sdugks_t *h, int64_t n);
 
 /* rho, u, v: [n_cells] host arrays (any may be NULL).  Synchronises. */
 int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v);
@@ -157,6 +165,15 @@ int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v);
  * With FP32DEV storage f is returned as w_i rho0 + (stored deviation). */
 int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G);
 int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double *G);
+
+/* Equilibrium state from macroscopic fields: f_i = feq_i(rho, u, v) on the
+ * device (the second-order discrete form of Eq. Feq, whose moments are rho
+ * and rho u, Eq. Macro), W = (rho, rho u, rho v), G = 0, and the residual
+ * snapshot = the velocity (rho u) / rho of that W.  rho, u, v: host arrays [n_cells] in the caller's order,
+ * rho > 0 and all finite (SDUGKS_EINVAL otherwise, state untouched).  With the
+ * original scheme the stored f~ of an equilibrium is f itself.  Clears the
+ * diverged flag.  Synchronises. */
+int sdugks_set_macros(sdugks_t *h, const double *rho, const double *u, const double *v);
 
 /* eps = sqrt(sum_j |u_j - u_j^snap|^2) / sqrt(sum_j |u_j^snap|^2) over cells
  * (unweighted), the residual of the paper's cavity case, against the snapshot
@@ -220,15 +237,27 @@ int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugk
 /* Replace the membership (continuous batching): waits for the batch stream.
  * If the new members pass the checks but the device tables cannot be
  * allocated (SDUGKS_ENOMEM) or filled (SDUGKS_EHIP), the batch is left with
- * no members: stepping it then advances nothing until members are set again.
+ * no members and marked failed: sdugks_batch_step and sdugks_batch_residual
+ * then return SDUGKS_EINVAL until a later sdugks_batch_set_members succeeds.
  * The same holds for the table refresh inside sdugks_batch_step. */
 int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_t n);
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n);
+
+/* Residual of every member (the definition of sdugks_residual, each against
+ * its own snapshot, then re-snapshotted) in one batched reduction launch and
+ * one synchronisation; bitwise the values sdugks_residual would return.
+ * eps: host [n members] in member order.  A member with a non-finite density
+ * or velocity gets NaN, refuses further steps, and the call returns
+ * SDUGKS_EDIVERGED after filling every entry. */
+int sdugks_batch_residual(sdugks_batch_t *b, double *eps);
 int sdugks_batch_destroy(sdugks_batch_t *b);
 
 /* Failure injection for tests: writes NaN into f of one cell and velocity
  * (caller cell order). */
 int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i);
+/* Failure injection for tests: the batch's next table rebuild fails with
+ * SDUGKS_ENOMEM (nothing is allocated). */
+int sdugks_debug_batch_fail(sdugks_batch_t *b);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,9 @@ int fail(int code, const std::string &msg)
     } while (0)
 
 constexpr size_t kAlign = 256;
+// Steps per replay of the long step graphs, in pairs (each pair returns every
+// instance to its buffer index).
+constexpr int64_t kGraphPairs = 16;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -120,17 +123,24 @@ struct sdugks_s {
     DevTiles dt{};
     DevBnd bq{};
     double *host4 = nullptr;     // pinned, 4 doubles
+    // steps replayed from captured graphs: [buffer index at launch][one pair,
+    // kGraphPairs pairs], captured on a private stream and launched on `stream`
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 
     template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(base + off); }
-    DevState state() const
+    // buffers of a step that reads buffer index c and writes c ^ 1
+    DevState state_at(int c) const
     {
         DevState s;
-        s.f = at<double>(L.off_f[cur]); s.W = at<double>(L.off_W[cur]); s.G = at<double>(L.off_G[cur]);
-        s.fo = at<double>(L.off_f[cur ^ 1]); s.Wo = at<double>(L.off_W[cur ^ 1]); s.Go = at<double>(L.off_G[cur ^ 1]);
-        s.f32 = at<float>(L.off_f[cur]);
-        s.fo32 = at<float>(L.off_f[cur ^ 1]);
+        s.f = at<double>(L.off_f[c]); s.W = at<double>(L.off_W[c]); s.G = at<double>(L.off_G[c]);
+        s.fo = at<double>(L.off_f[c ^ 1]); s.Wo = at<double>(L.off_W[c ^ 1]); s.Go = at<double>(L.off_G[c ^ 1]);
+        s.f32 = at<float>(L.off_f[c]);
+        s.fo32 = at<float>(L.off_f[c ^ 1]);
         return s;
     }
+    DevState state() const { return state_at(cur); }
     bool dev32() const { return precision == SDUGKS_FP32DEV; }
     DevScratch scratch() const { return {at<double>(L.off_fbp), at<double>(L.off_sg)}; }
 };
@@ -157,6 +167,12 @@ struct sdugks_batch_s {
     hipGraphExec_t exec_k = nullptr;
     int device = 0;
     std::vector<int> cur_at_fill;     // members' buffer indices when the tables were filled
+    bool failed = false;              // a table rebuild failed: no members until set_members succeeds
+    bool fail_next_build = false;     // failure injection for tests
+    // batched residual: job table (pinned host copy and device) and results
+    int cap_jobs = 0;
+    ReduceJob *h_jobs = nullptr, *d_jobs = nullptr;
+    double *h_out = nullptr, *d_out = nullptr;
 };
 
 namespace {
@@ -231,18 +247,64 @@ int reduce(sdugks_t *h, int update_snap, double out[4])
     return SDUGKS_OK;
 }
 
-int enqueue_step(sdugks_t *h)
+// One step that reads buffer index c, on stream st (no bookkeeping).
+int launch_step_at(sdugks_t *h, int c, hipStream_t st)
 {
-    DevState s = h->state();
+    DevState s = h->state_at(c);
+    const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
     if (h->mb.n_tiles > 0) {
-        HIPCHK(launch_step_tiled(h->dm, h->dt, s, h->macro == SDUGKS_MACRO_LAGGED, h->dev32(), h->block, h->stream));
+        HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->dev32(), h->block, st));
     } else {
         DevScratch x = h->scratch();
-        HIPCHK(launch_grad(h->dm, s, x, h->stream));
-        HIPCHK(launch_flux_update(h->dm, s, x, h->macro == SDUGKS_MACRO_LAGGED, h->stream));
+        HIPCHK(launch_grad(h->dm, s, x, st));
+        HIPCHK(launch_flux_update(h->dm, s, x, lagged, st));
     }
+    return SDUGKS_OK;
+}
+
+int enqueue_step(sdugks_t *h)
+{
+    int rc = launch_step_at(h, h->cur, h->stream);
+    if (rc) return rc;
     h->cur ^= 1;
     h->step++;
+    return SDUGKS_OK;
+}
+
+void release_step_graphs(sdugks_t *h)
+{
+    for (int c = 0; c < 2; c++)
+        for (int k = 0; k < 2; k++) {
+            if (h->exec[c][k]) hipGraphExecDestroy(h->exec[c][k]);
+            if (h->graph[c][k]) hipGraphDestroy(h->graph[c][k]);
+            h->exec[c][k] = nullptr;
+            h->graph[c][k] = nullptr;
+        }
+}
+
+// Capture `pairs` pairs of steps starting from buffer index c into a graph
+// (on the handle's private capture stream; the graph is launched on its
+// stream).
+int capture_step_graph(sdugks_t *h, int c, int64_t pairs, hipGraph_t &graph, hipGraphExec_t &exec)
+{
+    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int rc = 0;
+    for (int64_t k = 0; k < pairs && !rc; k++) {
+        rc = launch_step_at(h, c, h->cap_stream);
+        if (!rc) rc = launch_step_at(h, c ^ 1, h->cap_stream);
+    }
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &gr);
+    if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
+    if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        hipGraphDestroy(gr);
+        exec = nullptr;
+        return fail(SDUGKS_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ie));
+    }
+    graph = gr;
     return SDUGKS_OK;
 }
 
@@ -609,6 +671,37 @@ int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G)
     return SDUGKS_OK;
 }
 
+int sdugks_set_macros(sdugks_t *h, const double *rho, const double *u, const double *v)
+{
+    if (!h || !rho || !u || !v) return fail(SDUGKS_EINVAL, "null argument");
+    const size_t nc = h->mb.nc, np = h->L.np;
+    for (size_t c = 0; c < nc; c++)
+        if (!(rho[c] > 0.0) || !std::isfinite(rho[c]) || !std::isfinite(u[c]) || !std::isfinite(v[c]))
+            return fail(SDUGKS_EINVAL, "set_macros: rho must be positive and rho, u, v finite (cell " +
+                                           std::to_string(c) + ")");
+    HIPCHK(hipSetDevice(h->device));
+    // the macros staged in the W rows the next step writes, in the internal order
+    std::vector<double> m3(3 * nc);
+    for (size_t k = 0; k < nc; k++) {
+        const size_t c = h->mb.perm[k];
+        m3[k] = rho[c];
+        m3[nc + k] = u[c];
+        m3[2 * nc + k] = v[c];
+    }
+    double *stage = h->at<double>(h->L.off_W[h->cur ^ 1]);
+    int rc = upload_rows(stage, m3, 3, nc, np, h->stream);
+    if (rc) return rc;
+    const bool dev = h->dev32();
+    HIPCHK(launch_set_equilibrium((int)nc, (int)np, stage, dev ? nullptr : h->at<double>(h->L.off_f[h->cur]),
+                                  dev ? h->at<float>(h->L.off_f[h->cur]) : nullptr, h->rho0,
+                                  h->at<double>(h->L.off_W[h->cur]), h->at<double>(h->L.off_G[h->cur]),
+                                  h->at<double>(h->L.off_snap), h->stream));
+    rc = sync_check(h);
+    if (rc) return rc;
+    h->diverged = false;
+    return SDUGKS_OK;
+}
+
 int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v)
 {
     if (!h) return fail(SDUGKS_EINVAL, "null handle");
@@ -624,6 +717,32 @@ int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v)
 }
 
 int sdugks_step(sdugks_t *h, int64_t n)
+{
+    if (!h) return fail(SDUGKS_EINVAL, "null handle");
+    if (n < 0) return fail(SDUGKS_EINVAL, "negative step count");
+    if (h->diverged) return fail(SDUGKS_EDIVERGED, "state is not finite; reset it with sdugks_set_state");
+    HIPCHK(hipSetDevice(h->device));
+    // whole runs of kGraphPairs pairs replay the long graph, the remaining
+    // pairs the one-pair graph, an odd last step is launched alone
+    int64_t pairs = n / 2;
+    const int64_t runs = pairs / kGraphPairs;
+    pairs -= runs * kGraphPairs;
+    const int c = h->cur;
+    int rc;
+    if (runs > 0) {
+        if (!h->exec[c][1] && (rc = capture_step_graph(h, c, kGraphPairs, h->graph[c][1], h->exec[c][1]))) return rc;
+        for (int64_t k = 0; k < runs; k++) HIPCHK(hipGraphLaunch(h->exec[c][1], h->stream));
+    }
+    if (pairs > 0) {
+        if (!h->exec[c][0] && (rc = capture_step_graph(h, c, 1, h->graph[c][0], h->exec[c][0]))) return rc;
+        for (int64_t k = 0; k < pairs; k++) HIPCHK(hipGraphLaunch(h->exec[c][0], h->stream));
+    }
+    h->step += 2 * (n / 2);
+    if (n & 1) return enqueue_step(h);
+    return SDUGKS_OK;
+}
+
+int sdugks_step_eager(sdugks_t *h, int64_t n)
 {
     if (!h) return fail(SDUGKS_EINVAL, "null handle");
     if (n < 0) return fail(SDUGKS_EINVAL, "negative step count");
@@ -734,6 +853,8 @@ int sdugks_destroy(sdugks_t *h)
     if (!h) return SDUGKS_OK;
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
+    release_step_graphs(h);
+    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->own) hipFree(h->base);
     hipHostFree(h->host4);
     delete h;
@@ -751,6 +872,9 @@ int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i)
 }
 
 namespace {
+
+const char *const kBatchFailedMsg =
+    "the batch lost its members when a table rebuild failed; set them again with sdugks_batch_set_members";
 
 size_t next_pow2(size_t x)
 {
@@ -872,7 +996,10 @@ int batch_build_tables(sdugks_batch_t *b)
 // members' buffer index without advancing them) must never be launched
 int batch_build(sdugks_batch_t *b)
 {
-    const int rc = batch_build_tables(b);
+    const int rc = b->fail_next_build ? fail(SDUGKS_ENOMEM, "batch table rebuild failed (injected)")
+                                      : batch_build_tables(b);
+    b->fail_next_build = false;
+    b->failed = rc != SDUGKS_OK;
     if (rc) {
         batch_release_graph(b);
         batch_release_groups(b);
@@ -963,9 +1090,6 @@ int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_
 }
 
 namespace {
-// Steps per replay of the long batch graph, in pairs (each pair returns every
-// member to its buffer parity).
-constexpr int64_t kGraphPairs = 16;
 
 // Capture `pairs` pairs of batched steps on the batch's stream into a graph.
 int batch_capture(sdugks_batch_t *b, int64_t pairs, hipGraph_t &graph, hipGraphExec_t &exec)
@@ -995,6 +1119,7 @@ int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
 {
     if (!b) return fail(SDUGKS_EINVAL, "null batch");
     if (n < 0) return fail(SDUGKS_EINVAL, "negative step count");
+    if (b->failed) return fail(SDUGKS_EINVAL, kBatchFailedMsg);
     for (sdugks_t *h : b->members)
         if (h->diverged) return fail(SDUGKS_EDIVERGED, "a batch member is not finite");
     if (n == 0) return SDUGKS_OK;
@@ -1036,11 +1161,69 @@ int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
     return SDUGKS_OK;
 }
 
+int sdugks_batch_residual(sdugks_batch_t *b, double *eps)
+{
+    if (!b || !eps) return fail(SDUGKS_EINVAL, "null argument");
+    if (b->failed) return fail(SDUGKS_EINVAL, kBatchFailedMsg);
+    const int n = (int)b->members.size();
+    if (n == 0) return SDUGKS_OK;
+    HIPCHK(hipSetDevice(b->device));
+    if (n > b->cap_jobs) {
+        HIPCHK(hipStreamSynchronize(b->stream));
+        hipHostFree(b->h_jobs); hipFree(b->d_jobs); hipHostFree(b->h_out); hipFree(b->d_out);
+        b->h_jobs = nullptr; b->d_jobs = nullptr; b->h_out = nullptr; b->d_out = nullptr;
+        b->cap_jobs = 0;
+        const size_t cap = next_pow2((size_t)n);
+        if (hipHostMalloc((void **)&b->h_jobs, cap * sizeof(ReduceJob), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&b->d_jobs, cap * sizeof(ReduceJob)) != hipSuccess ||
+            hipHostMalloc((void **)&b->h_out, cap * 4 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&b->d_out, cap * 4 * sizeof(double)) != hipSuccess)
+            return fail(SDUGKS_ENOMEM, "allocation of the batched residual buffers failed");
+        b->cap_jobs = (int)cap;
+    }
+    for (int k = 0; k < n; k++) {
+        const sdugks_t *h = b->members[k];
+        b->h_jobs[k] = ReduceJob{h->mb.nc, (int32_t)h->L.np, h->at<double>(h->L.off_W[h->cur]),
+                                 h->at<double>(h->L.off_area), h->at<double>(h->L.off_snap),
+                                 h->at<double>(h->L.off_part)};
+    }
+    int rc = batch_join(b, true);
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(b->d_jobs, b->h_jobs, n * sizeof(ReduceJob), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(launch_reduce_batch(b->d_jobs, n, b->d_out, b->stream));
+    HIPCHK(hipMemcpyAsync(b->h_out, b->d_out, n * 4 * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    bool bad = false;
+    for (int k = 0; k < n; k++) {
+        const double *r = b->h_out + 4 * k;
+        if (r[3] != 0.0) {
+            b->members[k]->diverged = true;
+            eps[k] = NAN;
+            bad = true;
+        } else {
+            eps[k] = r[1] > 0 ? std::sqrt(r[0]) / std::sqrt(r[1]) : INFINITY;
+        }
+    }
+    return bad ? fail(SDUGKS_EDIVERGED, "non-finite density or velocity in a batch member (its residual is NaN)")
+               : SDUGKS_OK;
+}
+
+int sdugks_debug_batch_fail(sdugks_batch_t *b)
+{
+    if (!b) return fail(SDUGKS_EINVAL, "null batch");
+    b->fail_next_build = true;
+    return SDUGKS_OK;
+}
+
 int sdugks_batch_destroy(sdugks_batch_t *b)
 {
     if (!b) return SDUGKS_OK;
     hipSetDevice(b->device);
     if (b->stream) hipStreamSynchronize(b->stream);
+    hipHostFree(b->h_jobs);
+    hipFree(b->d_jobs);
+    hipHostFree(b->h_out);
+    hipFree(b->d_out);
     batch_release_graph(b);
     batch_release_groups(b);
     if (b->ev) hipEventDestroy(b->ev);

@@ -118,6 +118,21 @@ hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int up
 // Boundary face fluxes on the state s (FP64 f, or the deviation form when
 // dev32), then their sums over the faces of `tag` (all when tag < 0).
 hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBnd &q, int dev32, int tag, hipStream_t st);
+// One member of a batched residual: its cells, current W, areas, snapshot
+// (re-snapshotted) and its own partial sums.
+struct ReduceJob {
+    int32_t nc, np;
+    const double *W;
+    const double *area;
+    double *snap;
+    double *partials;
+};
+// Residuals of n members at once: out [n][4] as launch_reduce's out4 each.
+hipError_t launch_reduce_batch(const ReduceJob *jobs, int n, double *out, hipStream_t st);
+// f = feq of the macros m3 = [3][np] (rho, u, v) (FP64 f, or with f32 the
+// FP32 deviation from w_i rho0), W, G = 0 and the residual snapshot.
+hipError_t launch_set_equilibrium(int nc, int np, const double *m3, double *f, float *f32, double rho0, double *W,
+                                  double *G, double *snap, hipStream_t st);
 // *p = NaN, p pointing at a double (bytes 8) or a float (bytes 4): failure injection.
 hipError_t launch_poke_nan(void *p, int bytes, hipStream_t st);
 

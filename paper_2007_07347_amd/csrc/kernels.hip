@@ -13,7 +13,9 @@
 //                   (Eq. MacroUpdate), feq^{n+1} and f^{n+1} (Eq. fn+1).
 //                   Four lanes per cell, one face each; the per-cell flux
 //                   sums are formed with lane shuffles in a fixed order.
-//   k_reduce*       residual of the cavity case, total mass, finiteness.
+//   k_reduce*       residual of the cavity case, total mass, finiteness (one
+//                   instance, or every member of a batch in one launch).
+//   k_set_equilibrium  f = feq of given macros (initial states).
 //
 // Every face is evaluated by both of its cells from bit-identical operands
 // (the mesh builder stores mirrored copies), so the two evaluations agree
@@ -21,6 +23,7 @@
 #include "device.h"
 
 #include "d2q9.h"
+#include "reduce.h"
 
 namespace sdg {
 
@@ -190,46 +193,56 @@ __global__ void __launch_bounds__(256) k_flux_update(DevMesh m, DevState s, DevS
     }
 }
 
-// Per-block partial sums in a fixed order; a second single-block pass adds them.
 __global__ void __launch_bounds__(256) k_reduce(int nc, int np, const double *__restrict__ W,
                                                const double *__restrict__ area, double *snap, int update,
                                                double *partials)
 {
-    __shared__ double red[4][256];
-    const int chunk = (nc + kReduceBlocks - 1) / kReduceBlocks;
-    const int lo = blockIdx.x * chunk, hi = min(nc, lo + chunk);
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    for (int c = lo + threadIdx.x; c < hi; c += blockDim.x) {
-        const double r = W[c];
-        const double U = W[np + c] / r, V = W[2 * np + c] / r;
-        const double su = snap[c], sv = snap[np + c];
-        a0 += (U - su) * (U - su) + (V - sv) * (V - sv);
-        a1 += su * su + sv * sv;
-        a2 += area[c] * r;
-        a3 += (isfinite(r) && isfinite(U) && isfinite(V)) ? 0.0 : 1.0;
-        if (update) { snap[c] = U; snap[np + c] = V; }
-    }
-    red[0][threadIdx.x] = a0; red[1][threadIdx.x] = a1; red[2][threadIdx.x] = a2; red[3][threadIdx.x] = a3;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) partials[threadIdx.x * kReduceBlocks + blockIdx.x] = red[threadIdx.x][0];
+    reduce_block(nc, np, W, area, snap, update, partials, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_reduce_final(const double *partials, double *out4)
 {
-    __shared__ double red[4][kReduceBlocks];
-    for (int k = 0; k < 4; k++) red[k][threadIdx.x] = partials[k * kReduceBlocks + threadIdx.x];
-    __syncthreads();
-    for (int w = kReduceBlocks / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int k = 0; k < 4; k++) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-        __syncthreads();
+    reduce_final(partials, out4);
+}
+
+// Batched residual: blockIdx.y selects the member.
+__global__ void __launch_bounds__(256) k_reduce_batch(const ReduceJob *jobs)
+{
+    const ReduceJob j = jobs[blockIdx.y];
+    reduce_block(j.nc, j.np, j.W, j.area, j.snap, 1, j.partials, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(256) k_reduce_final_batch(const ReduceJob *jobs, double *out)
+{
+    reduce_final(jobs[blockIdx.x].partials, out + 4 * (size_t)blockIdx.x);
+}
+
+// Equilibrium state from per-cell macros m3 = [3][np] (rho, u, v): f = feq
+// (Eq. Feq; its moments are the macros, Eq. Macro), stored as f or, with f32,
+// as the deviation feq - w_i rho0 in FP32; W = (rho, rho u, rho v); G = 0;
+// the residual snapshot = the velocity of W.
+__global__ void __launch_bounds__(256) k_set_equilibrium(int nc, int np, const double *m3, double *f, float *f32,
+                                                        double rho0, double *W, double *G, double *snap)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    const double r = m3[c], ux = m3[np + c], uy = m3[2 * np + c];
+#pragma unroll
+    for (int i = 0; i < 9; i++) {
+        const double fe = feq_one(kW[i], kEx[i], kEy[i], r, ux, uy);
+        if (f32) f32[(size_t)i * np + c] = (float)(fe - kW[i] * rho0);
+        else f[(size_t)i * np + c] = fe;
     }
-    if (threadIdx.x < 4) out4[threadIdx.x] = red[threadIdx.x][0];
+    const double mx = r * ux, my = r * uy;
+    W[c] = r;
+    W[np + c] = mx;
+    W[2 * np + c] = my;
+    G[c] = 0.0;
+    G[np + c] = 0.0;
+    G[2 * np + c] = 0.0;
+    // the velocity exactly as the residual reduction derives it from W
+    snap[c] = mx / r;
+    snap[np + c] = my / r;
 }
 
 __global__ void k_poke_nan(void *p, int bytes)
@@ -266,6 +279,23 @@ hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int up
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kReduceBlocks), 0, st, partials, out4);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_batch(const ReduceJob *jobs, int n, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_reduce_batch, dim3(kReduceBlocks, n), dim3(256), 0, st, jobs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_final_batch, dim3(n), dim3(kReduceBlocks), 0, st, jobs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_equilibrium(int nc, int np, const double *m3, double *f, float *f32, double rho0, double *W,
+                                  double *G, double *snap, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_set_equilibrium, dim3((nc + 255) / 256), dim3(256), 0, st, nc, np, m3, f, f32, rho0, W, G,
+                       snap);
     return hipGetLastError();
 }
 

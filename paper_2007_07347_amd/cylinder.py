@@ -126,17 +126,6 @@ def dominant_frequency(t, x):
     return k / (n * dt)
 
 
-def equilibrium(rho, ux, uy):
-    """D2Q9 second-order equilibrium of per-cell macros, [n][9] (initial
-    states only)."""
-    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
-    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
-    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
-    eu = ux[:, None] * ex + uy[:, None] * ey
-    uu = (ux * ux + uy * uy)[:, None]
-    return w * rho[:, None] * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu)
-
-
 def kicked_start(solver, mesh, bcs, u_inf, amp, center=(1.5, 0.0), width=0.5, **geometry_kw):
     """Free stream with a transverse velocity bump amp * u_inf *
     exp(-|x - center|^2 / width) in the near wake, at equilibrium: a seed for
@@ -145,8 +134,7 @@ def kicked_start(solver, mesh, bcs, u_inf, amp, center=(1.5, 0.0), width=0.5, **
     g = geometry(mesh, bcs, **geometry_kw)
     n = len(g["cx"])
     v = amp * u_inf * np.exp(-((g["cx"] - center[0]) ** 2 + (g["cy"] - center[1]) ** 2) / width)
-    rho, u = np.ones(n), np.full(n, u_inf)
-    solver.set_state(equilibrium(rho, u, v), np.c_[rho, rho * u, rho * v])
+    solver.set_macros(np.ones(n), np.full(n, u_inf), v)
 
 
 def run_shedding(sd, mesh, bcs, re, u_inf=0.1, d=1.0, t_transient=600.0, t_sample=400.0, sample_every=200,

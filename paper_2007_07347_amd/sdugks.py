@@ -51,6 +51,8 @@ _sig = {
     "sdugks_tiling": [_P, _P, C.c_int32, _P, _P, _P, _P, _P],
     "sdugks_create": [_P, _P, C.c_int32, _P, _P, _P, C.c_size_t, _P],
     "sdugks_step": [_P, C.c_int64],
+    "sdugks_step_eager": [_P, C.c_int64],
+    "sdugks_set_macros": [_P, _P, _P, _P],
     "sdugks_macros": [_P, _P, _P, _P],
     "sdugks_get_state": [_P, _P, _P, _P],
     "sdugks_set_state": [_P, _P, _P, _P],
@@ -64,6 +66,8 @@ _sig = {
     "sdugks_batch_create": [_P, C.c_int32, _P, _P],
     "sdugks_batch_set_members": [_P, _P, C.c_int32],
     "sdugks_batch_step": [_P, C.c_int64],
+    "sdugks_batch_residual": [_P, _P],
+    "sdugks_debug_batch_fail": [_P],
     "sdugks_batch_destroy": [_P],
     "sdugks_debug_poison": [_P, C.c_int32, C.c_int32],
 }
@@ -176,6 +180,10 @@ class Solver:
     def step(self, n=1):
         _check(_lib.sdugks_step(self._h, int(n)))
 
+    def step_eager(self, n=1):
+        """The same steps launched one by one (no graph replay)."""
+        _check(_lib.sdugks_step_eager(self._h, int(n)))
+
     def step_profiled(self, n):
         ms = np.zeros(8)
         names = (C.c_char_p * 8)()
@@ -201,6 +209,13 @@ class Solver:
         W = np.ascontiguousarray(W, dtype=np.float64).reshape(n, 3)
         G = np.zeros((n, 3)) if G is None else np.ascontiguousarray(G, dtype=np.float64).reshape(n, 3)
         _check(_lib.sdugks_set_state(self._h, _ptr(f), _ptr(W), _ptr(G)))
+
+    def set_macros(self, rho, u, v):
+        """Equilibrium state of the given per-cell density and velocity
+        (computed on the device)."""
+        n = self.n_cells
+        arrs = [np.ascontiguousarray(np.broadcast_to(np.asarray(x, dtype=np.float64), (n,))) for x in (rho, u, v)]
+        _check(_lib.sdugks_set_macros(self._h, *[_ptr(a) for a in arrs]))
 
     def residual(self):
         e = C.c_double()
@@ -261,14 +276,36 @@ class Batch:
                                         C.c_void_p(stream.cuda_stream) if stream is not None else None, C.byref(b)))
         self._b = b
 
+    def _call(self, rc):
+        # a failed table rebuild leaves the library's batch without members
+        if rc in (ENOMEM, EHIP):
+            self.members = []
+        _check(rc)
+
     def set_members(self, members):
         members = list(members)
         arr = (C.c_void_p * len(members))(*[m.handle for m in members])
-        _check(_lib.sdugks_batch_set_members(self._b, arr, len(members)))
+        self._call(_lib.sdugks_batch_set_members(self._b, arr, len(members)))
         self.members = members
 
     def step(self, n=1):
-        _check(_lib.sdugks_batch_step(self._b, int(n)))
+        self._call(_lib.sdugks_batch_step(self._b, int(n)))
+
+    def residuals(self):
+        """Residual of every member in member order (one launch, one
+        synchronisation); NaN for a member whose state is not finite, and
+        SdugksError(EDIVERGED) raised after all entries are filled."""
+        eps = np.zeros(len(self.members))
+        rc = _lib.sdugks_batch_residual(self._b, _ptr(eps) if len(eps) else None)
+        if rc == EDIVERGED:
+            err = SdugksError(rc, _lib.sdugks_last_error().decode())
+            err.residuals = eps
+            raise err
+        self._call(rc)
+        return eps
+
+    def debug_fail_next_build(self):
+        _check(_lib.sdugks_debug_batch_fail(self._b))
 
     def close(self):
         lib = getattr(self, "_lib", None)

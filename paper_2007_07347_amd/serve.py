@@ -12,6 +12,13 @@ frees the slot and the memory, and the next queued request is admitted
 before the next chunk: requests that arrive while others run join the
 running batch.
 
+Admission overlaps the GPU: when the backend offers create_async(), the
+admitted request's instance (mesh build on the host, upload on a stream of
+its own) is made on a worker thread while the batch keeps stepping, and joins
+the batch at the first chunk boundary after it is ready.  When the batch
+offers residuals(), every member's residual comes from one batched reduction
+and one synchronisation per chunk.
+
 An instance whose residual has stopped falling while still above the
 tolerance (no 20 % gain over `stall_checks` checks) is handed to the
 backend's optional escalate(): the GPU backend continues it from its current
@@ -24,8 +31,12 @@ included).  The backend interface keeps the policy testable without a GPU:
     backend.bytes(req) -> int                 device bytes the instance needs
     backend.create(req) -> instance           instance.step(n), .residual(),
                                               .macros(), .close(), .n_cells
+    backend.create_async(req) -> future       optional: .done(), .result() -> instance
     backend.batch(instances) -> batch         batch.step(n), .set_members(list),
-                                              .close()
+                                              .close(); optional .residuals() ->
+                                              one residual per member, raising
+                                              an error with .code == -4 and
+                                              .residuals (NaN where not finite)
     backend.escalate(req, inst, room)         optional: (instance, bytes) that
         -> (instance, int) or None            continues inst, or None
 """
@@ -98,20 +109,22 @@ class Server:
         """Serve a finite trace; returns (results in request order, stats)."""
         pending = sorted(requests, key=lambda r: r.arrival)
         queue: List[Request] = []
+        staging = []                        # [req, future, bytes, admitted_at]: instances being made
         active = []                         # [req, instance, bytes, admitted_at, steps, best, stalled, escalated]
         results = {}
         used = 0
         batch = None
         members_changed = False
         cell_updates = 0
+        make_async = getattr(self.backend, "create_async", None)
         t0 = self.clock()
         now = lambda: self.clock() - t0     # noqa: E731
-        while pending or queue or active:
+        while pending or queue or active or staging:
             t = now()
             while pending and pending[0].arrival <= t:
                 queue.append(pending.pop(0))
             # admission, FIFO: the head waits until it fits (no overtaking)
-            while queue and len(active) < self.max_slots:
+            while queue and len(active) + len(staging) < self.max_slots:
                 req = queue[0]
                 need = self.backend.bytes(req)
                 if need > self.budget:
@@ -123,11 +136,25 @@ class Server:
                 if used + need > self.budget:
                     break
                 queue.pop(0)
-                inst = self.backend.create(req)
                 used += need
-                active.append([req, inst, need, now(), 0, math.inf, 0, False])
-                members_changed = True
                 self.log.append((now(), "admit", req.rid, need))
+                if make_async is not None:
+                    staging.append([req, make_async(req), need, now()])
+                else:
+                    active.append([req, self.backend.create(req), need, now(), 0, math.inf, 0, False])
+                    members_changed = True
+            # instances made on the worker join at this chunk boundary; with
+            # nothing running, wait for the first one instead of spinning
+            if staging and not active:
+                staging[0][1].result()
+            still = []
+            for st in staging:
+                if st[1].done():
+                    active.append([st[0], st[1].result(), st[2], st[3], 0, math.inf, 0, False])
+                    members_changed = True
+                else:
+                    still.append(st)
+            staging = still
             if not active:
                 if pending:
                     self.sleep(max(0.0, min(pending[0].arrival - now(), 0.05)))
@@ -141,18 +168,32 @@ class Server:
             for a in active:
                 a[4] += self.interval
                 cell_updates += a[1].n_cells * self.interval
+            # every residual, from one batched reduction when the batch has it
+            eps_all = None
+            if hasattr(batch, "residuals"):
+                try:
+                    eps_all = list(batch.residuals())
+                except Exception as e:          # some member not finite: NaN marks it
+                    if getattr(e, "code", None) != -4:
+                        raise
+                    eps_all = list(e.residuals)
             # poll every instance, then change the membership once, then free
             keep, retired = [], []
             can_escalate = self.stall_checks > 0 and hasattr(self.backend, "escalate")
-            for a in active:
+            for k, a in enumerate(active):
                 req, inst, need, t_adm, steps = a[:5]
                 status = None
-                try:
-                    eps = inst.residual()
-                except Exception as e:          # non-finite state: only this request fails
-                    if getattr(e, "code", None) != -4:
-                        raise
-                    eps, status = math.nan, "diverged"
+                if eps_all is not None:
+                    eps = eps_all[k]
+                    if math.isnan(eps):
+                        status = "diverged"
+                else:
+                    try:
+                        eps = inst.residual()
+                    except Exception as e:      # non-finite state: only this request fails
+                        if getattr(e, "code", None) != -4:
+                            raise
+                        eps, status = math.nan, "diverged"
                 if status is None:
                     if eps <= self.tol:
                         status = "converged"
@@ -260,13 +301,19 @@ class SequentialServer(Server):
 class GpuBackend:
     """Backend on libsdugks: one solver per request (its device memory a torch
     tensor of sdugks_state_bytes), one batch for all admitted solvers; a
-    stalled FP32-deviation solver is continued by an FP64 one."""
+    stalled FP32-deviation solver is continued by an FP64 one.  create_async()
+    builds a solver on a worker thread (the library's mesh build and upload
+    release the interpreter lock) on a stream of its own, so that neither its
+    host work nor its synchronous uploads wait for the running batch."""
 
-    def __init__(self, precision=None, **defaults):
+    def __init__(self, precision=None, workers=2, **defaults):
         from . import sdugks
         self.sd = sdugks
         self.precision = sdugks.FP32DEV if precision is None else precision
         self.defaults = defaults
+        self.workers = int(workers)
+        self._pool = None
+        self._bytes = {}
 
     def _kw(self, req):
         kw = dict(self.defaults)
@@ -275,10 +322,24 @@ class GpuBackend:
         return kw
 
     def bytes(self, req):
-        return self.sd.state_bytes(req.mesh, req.bcs, **self._kw(req))
+        # the host mesh build behind this is paid once per request
+        key = (id(req), self.precision)
+        if key not in self._bytes:
+            self._bytes[key] = self.sd.state_bytes(req.mesh, req.bcs, **self._kw(req))
+        return self._bytes[key]
 
-    def create(self, req):
-        return self.sd.Solver(req.mesh, req.bcs, **self._kw(req))
+    def create(self, req, stream=None):
+        return self.sd.Solver(req.mesh, req.bcs, stream=stream, **self._kw(req))
+
+    def _create_on_side_stream(self, req):
+        import torch
+        return self.create(req, stream=torch.cuda.Stream())
+
+    def create_async(self, req):
+        if self._pool is None:
+            from concurrent.futures import ThreadPoolExecutor
+            self._pool = ThreadPoolExecutor(max_workers=self.workers, thread_name_prefix="sdugks-admit")
+        return self._pool.submit(self._create_on_side_stream, req)
 
     def batch(self, instances):
         return self.sd.Batch(instances)
@@ -291,6 +352,11 @@ class GpuBackend:
         need = self.sd.state_bytes(req.mesh, req.bcs, **kw)
         if need > room:
             return None
-        new = self.sd.Solver(req.mesh, req.bcs, **kw)
+        new = self.sd.Solver(req.mesh, req.bcs, stream=getattr(inst, "stream", None), **kw)
         new.set_state(*inst.state())
         return new, need
+
+    def close(self):
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+            self._pool = None

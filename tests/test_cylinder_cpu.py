@@ -21,15 +21,6 @@ def test_axis_velocity_is_exact_for_linear_fields():
     assert np.abs(cylinder.axis_velocity(cx, cy, u, xs) - 0.1 * (xs - 3.0)).max() <= 1e-12
 
 
-def test_equilibrium_moments():
-    rho, u, v = np.array([1.0, 1.2]), np.array([0.1, -0.05]), np.array([0.0, 0.03])
-    f = cylinder.equilibrium(rho, u, v)
-    ex = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1.0])
-    ey = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1.0])
-    assert np.allclose(f.sum(1), rho, atol=1e-15)
-    assert np.allclose(f @ ex, rho * u, atol=1e-15) and np.allclose(f @ ey, rho * v, atol=1e-15)
-
-
 def test_golden_paper_cylinder_values():
     """The transcribed paper values are consistent with what the paper says
     of them: drag falls and the bubble grows with Re over the steady range, and

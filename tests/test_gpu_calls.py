@@ -1,0 +1,154 @@
+"""GPU tests of the calls around the step: the equilibrium set from macros
+against the oracle's equilibrium, graph-replayed stepping against launch by
+launch, the batched residual against the per-instance one, and the batch's
+state after a failed table rebuild."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import meshgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2007_07347_amd import sdugks
+    return sdugks
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("prec", ["f64", "fp32dev"])
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_set_macros_is_oracle_equilibrium(sd, oracle_mod, prec, scheme):
+    """f = feq(rho, u, v) per cell (Eq. Feq), W = (rho, rho u, rho v), G = 0,
+    element by element against the oracle's equilibrium: 1e-15 relative in
+    FP64; in FP32 deviation storage the stored deviation is the rounded
+    FP32 value of feq - w_i rho0 (half an FP32 ulp of it, plus FP64 rounding)."""
+    say("set_macros", prec, "scheme", scheme)
+    mesh, bcs = meshgen.cavity(23)
+    p = sd.FP64 if prec == "f64" else sd.FP32DEV
+    g = sd.Solver(mesh, bcs, nu=1e-3, cfl=0.5, precision=p, scheme=scheme)
+    rng = np.random.default_rng(5)
+    n = g.n_cells
+    rho = 1.0 + 0.05 * rng.uniform(-1, 1, n)
+    u, v = 0.1 * rng.uniform(-1, 1, n), 0.1 * rng.uniform(-1, 1, n)
+    g.set_macros(rho, u, v)
+    f, W, G = g.state()
+    ref = np.array([oracle_mod.feq(rho[c], u[c], v[c]) for c in range(n)])
+    w = oracle_mod.feq(1.0, 0.0, 0.0)
+    if prec == "f64":
+        assert np.abs(f - ref).max() <= 1e-15 * np.abs(ref).max()
+    else:
+        dev = ref - w[None, :]
+        assert np.all(np.abs((f - w[None, :]) - dev) <= 0.5 * np.spacing(np.abs(dev).astype(np.float32)) + 1e-16)
+    assert np.array_equal(W[:, 0], rho)
+    assert np.abs(W[:, 1] - rho * u).max() <= 1e-16 and np.abs(W[:, 2] - rho * v).max() <= 1e-16
+    assert not G.any()
+    # the residual snapshot is the new velocity field: no change, residual 0
+    assert g.residual() == 0.0
+    with pytest.raises(sd.SdugksError):
+        g.set_macros(np.where(np.arange(n) == 7, -1.0, rho), u, v)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "fp32dev"])
+@pytest.mark.parametrize("case", ["cavity", "couette_two_kernel"])
+def test_graph_replay_is_bitwise_eager(sd, prec, case):
+    """sdugks_step replays captured graphs (32 and 2 steps, an odd step alone,
+    from either buffer index); sdugks_step_eager launches one kernel per step:
+    identical bits after mixed step counts."""
+    say("graph replay", case, prec)
+    if case == "cavity":
+        mesh, bcs = meshgen.cavity(40)
+        kw = dict(nu=1e-3, cfl=0.5, precision=sd.FP64 if prec == "f64" else sd.FP32DEV,
+                  tile_cells=32, block_threads=128)
+    else:
+        if prec != "f64":
+            pytest.skip("the two-kernel step stores f in FP64 only")
+        mesh, bcs = meshgen.couette(4, 32, 0.1)
+        kw = dict(nu=0.01, cfl=0.5, tile_cells=-1)
+    a = sd.Solver(mesh, bcs, **kw)
+    b = sd.Solver(mesh, bcs, **kw)
+    f, W, G = meshgen.random_state(a.n_cells, seed=3, amp=0.02)
+    a.set_state(f, W)
+    b.set_state(f, W)
+    for n in (1, 70, 33, 2, 3, 64):
+        a.step(n)
+        b.step_eager(n)
+        fa, Wa, _ = a.state()
+        fb, Wb, _ = b.state()
+        assert np.array_equal(fa, fb) and np.array_equal(Wa, Wb), n
+    assert a.info()["step"] == b.info()["step"] == 173
+    a.close()
+    b.close()
+
+
+def test_batch_residual_is_bitwise_per_instance(sd):
+    """One batched reduction for all members gives bitwise the residuals of
+    sdugks_residual on each (and re-snapshots like it); a member whose f was
+    poisoned gets NaN once a step has carried the NaN into its macros, and the
+    call reports divergence after filling every entry."""
+    import torch
+    sizes = (17, 40, 9, 64)
+    mk = lambda: [sd.Solver(*meshgen.cavity(n), nu=1e-3, cfl=0.5, precision=sd.FP32DEV if n % 2 else sd.FP64)  # noqa: E731
+                  for n in sizes]
+    A, B = mk(), mk()
+    for s in A + B:
+        s.step(30)
+    ba = sd.Batch(A)
+    for rnd in range(3):
+        eps_b = ba.residuals()
+        eps_s = np.array([s.residual() for s in B])
+        say("batch residuals", eps_b, eps_s)
+        assert np.array_equal(eps_b, eps_s), rnd
+        ba.step(20)
+        for s in B:
+            s.step(20)
+    torch.cuda.synchronize()
+    A[2].poison(3, 4)
+    ba.step(2)                            # the NaN in f reaches W through the face fluxes
+    with pytest.raises(sd.SdugksError) as ei:
+        ba.residuals()
+    assert ei.value.code == sd.EDIVERGED
+    r = ei.value.residuals
+    assert math.isnan(r[2]) and np.isfinite(np.delete(r, 2)).all()
+    ba.close()
+    for s in A + B:
+        s.close()
+
+
+def test_batch_after_failed_rebuild(sd):
+    """A table rebuild that fails leaves the batch without members: stepping
+    and the batched residual are refused (not a silent no-op), the Python
+    batch lists no members, and setting members again restores it."""
+    sol = [sd.Solver(*meshgen.cavity(n), nu=1e-3, cfl=0.5) for n in (12, 20)]
+    b = sd.Batch(sol)
+    b.step(4)
+    b.debug_fail_next_build()
+    with pytest.raises(sd.SdugksError) as ei:
+        b.set_members(sol[:1])
+    assert ei.value.code == sd.ENOMEM and b.members == []
+    with pytest.raises(sd.SdugksError) as ei:
+        b.step(2)
+    assert ei.value.code == sd.EINVAL
+    with pytest.raises(sd.SdugksError):
+        b.residuals()
+    b.set_members(sol)
+    before = sol[0].info()["step"]
+    b.step(2)
+    assert sol[0].info()["step"] == before + 2
+    b.residuals()                         # the first check after rest is +inf by definition
+    b.step(2)
+    assert np.isfinite(b.residuals()).all()
+    b.close()
+    for s in sol:
+        s.close()

@@ -179,6 +179,37 @@ def test_cylinder_200k_window(sd, oracle_mod):
     compare(g, o, "cylinder200k")
 
 
+@pytest.mark.parametrize("case", ["cavity256_t32_b128", "cylinder200k_t64_b256"])
+def test_full_size_generic_state_window(sd, oracle_mod, case):
+    """Full-size meshes from a seeded generic state (every term of the step
+    active in every cell from the first step): the 256 x 256 cavity at Re 1000
+    on the 32-cell / 128-thread schedule and the 200,000-triangle cylinder at
+    Re 40 on the 64-cell / 256-thread schedule, 40 steps, FP64, compared with
+    the oracle after the first step and after the 40th."""
+    if case.startswith("cavity"):
+        mesh, bcs = meshgen.cavity(256)
+        kw = dict(nu=0.1 / 1000, cfl=0.5)
+        sched = dict(tile_cells=32, block_threads=128)
+    else:
+        mesh, bcs = meshgen.cylinder_ogrid(400, 250, seed=0)
+        kw = dict(nu=0.1 / 40, cfl=0.5, u0=0.1)
+        sched = dict(tile_cells=64, block_threads=256)
+    say("full-size generic window", case)
+    g = sd.Solver(mesh, bcs, **sched, **kw)
+    o = oracle_mod.Oracle(mesh, bcs, **kw)
+    f, W, G = meshgen.random_state(o.n_cells, seed=23, amp=0.02)
+    G[:] = 0.0
+    o.set_state(f, W, G)
+    g.set_state(f, W, G)
+    o.step(1)
+    g.step(1)
+    compare(g, o, f"{case} step 1")
+    o.step(39)
+    g.step(39)
+    compare(g, o, f"{case} step 40")
+    assert g.mass() == pytest.approx(o.mass(), rel=1e-13)
+
+
 def test_fused_and_two_kernel_paths_agree(sd):
     """The fused tiled step and the two-kernel step on the full 200k-cell
     cylinder mesh, several tile shapes: equal to rounding after 50 steps."""

@@ -295,3 +295,73 @@ def test_batch_signature_separates_member_sets():
     assert autotune.batch_signature(a) == autotune.batch_signature(list(a))
     assert autotune.batch_signature(a) != autotune.batch_signature(b)
     assert autotune.batch_signature(a) != autotune.batch_signature(a[:1])
+
+
+# ---- admission on a worker and one batched residual per chunk
+class SimFuture:
+    """Ready once the simulated clock passes `ready_at`."""
+
+    def __init__(self, clock, ready_at, value):
+        self.clock, self.ready_at, self.value = clock, ready_at, value
+
+    def done(self):
+        return self.clock.t >= self.ready_at
+
+    def result(self):
+        if not self.done():                 # waiting costs the time left
+            self.clock.t = self.ready_at
+        return self.value
+
+
+class ResidualBatch(FakeBatch):
+    def residuals(self):
+        out, bad = [], False
+        for m in self.members:
+            try:
+                out.append(m.residual())
+            except RuntimeError:
+                out.append(math.nan)
+                bad = True
+        if bad:
+            e = RuntimeError("not finite")
+            e.code, e.residuals = -4, out
+            raise e
+        return out
+
+
+class AsyncBackend(FakeBackend):
+    """Instances take `make_s` simulated seconds to build on the worker."""
+
+    def __init__(self, clock, make_s=0.01):
+        super().__init__(clock)
+        self.make_s, self.made_at = make_s, {}
+
+    def create_async(self, req):
+        inst = self.create(req)
+        self.made_at[req.rid] = self.clock.t + self.make_s
+        return SimFuture(self.clock, self.clock.t + self.make_s, inst)
+
+    def batch(self, instances):
+        return ResidualBatch(instances, self.clock, self.log)
+
+
+def test_async_admission_overlaps_the_running_batch():
+    """A request admitted while another runs is built on the worker; the
+    batch keeps stepping meanwhile (chunks without it), and it joins at the
+    first chunk boundary after it is ready.  Budget accounting includes the
+    instances still being built; a poisoned member is isolated by the
+    batched residual."""
+    clock = SimClock()
+    be = AsyncBackend(clock, make_s=0.01)
+    specs = [(0.0, 10, {"need": 40_000}), (0.001, 10, {"need": 3000}), (0.001, 10, {"need": 5000, "poison": True}),
+             (0.002, 10, {"need": 1000})]
+    srv = Server(be, budget_bytes=3 * 1000, clock=clock, sleep=clock.sleep, interval=1000)
+    res, stats = srv.run(reqs(specs))
+    assert [r.status for r in res] == ["converged", "converged", "diverged", "converged"]
+    batches = [m for kind, m in be.log if kind == "batch"]
+    # request 0 ran alone while 1 and 2 were being built, then with them
+    first_joint = next(k for k, m in enumerate(batches) if 1 in m)
+    assert first_joint > 1 and all(m == (0,) for m in batches[:first_joint])
+    t_admit = {rid: t for t, ev, rid, _ in srv.log if ev == "admit"}
+    assert t_admit[3] >= min(res[1].finished, res[2].finished)   # 3 waited for budget, FIFO
+    assert all(inst.closed for inst in be.live.values())
