@@ -59,9 +59,15 @@ enum {
  * tag's edges shifted by (shift_x, shift_y). */
 enum { SDUGKS_BC_WALL = 1, SDUGKS_BC_INLET = 2, SDUGKS_BC_OUTLET = 3, SDUGKS_BC_PERIODIC = 4, SDUGKS_BC_SYMMETRY = 5 };
 
-/* Storage precision of f: FP64, or FP32 holding the deviation f - w_i rho0
- * (density, momentum, mass and residual stay FP64). */
-enum { SDUGKS_FP64 = 0, SDUGKS_FP32DEV = 1 };
+/* Precision of f.  FP64: stored and computed in FP64.  FP32DEV: stored in
+ * FP32 as the deviation f - w_i rho0 and advected in FP32 (fbar+, gradients,
+ * face values and fluxes; compensated per-cell flux sums), with density,
+ * momentum, their update, the macroscopic flux, mass and residual in FP64;
+ * the rounding of its face arithmetic keeps the velocity residual from
+ * falling below a few 1e-8 on fine meshes.  FP32NEQ: the non-equilibrium
+ * part f - feq(rho, u) stored in FP32 (half the bytes of FP64 f), every
+ * operation of the step in FP64; converges like FP64. */
+enum { SDUGKS_FP64 = 0, SDUGKS_FP32DEV = 1, SDUGKS_FP32NEQ = 2 };
 
 /* Time level of the macroscopic flux of Eq. (MacroFlux) used by
  * Eq. (MacroUpdate): this step's face fluxes (CURRENT, default) or the previous
@@ -101,8 +107,8 @@ typedef struct {
     double tau;                   /* relaxation time; > 0 overrides nu */
     double cfl;                   /* dt = cfl * h_min / sqrt(2) (h_j = 2 * min centroid-to-face distance) */
     double dt;                    /* > 0 overrides cfl */
-    double rho0, u0, v0;          /* initial uniform equilibrium; rho0 is also the FP32DEV offset */
-    int32_t precision;            /* SDUGKS_FP64 or SDUGKS_FP32DEV */
+    double rho0, u0, v0;          /* initial uniform equilibrium; rho0 is also the offset of FP32 storage */
+    int32_t precision;            /* SDUGKS_FP64, SDUGKS_FP32DEV or SDUGKS_FP32NEQ */
     int32_t macro_flux;           /* SDUGKS_MACRO_CURRENT (default) or SDUGKS_MACRO_LAGGED */
     int32_t reorder;              /* two-kernel step: 1 = reverse Cuthill-McKee cell order inside the
                                      library (the fused step orders cells tile by tile instead) */
@@ -162,7 +168,10 @@ int sdugks_macros(sdugks_t *h, double *rho, double *u, double *v);
 
 /* Full state: f [n_cells][9], W [n_cells][3], G [n_cells][3] (the stored
  * macroscopic flux of the lagged mode; zeros otherwise).  Any may be NULL.
- * With FP32DEV storage f is returned as w_i rho0 + (stored deviation). */
+ * With FP32 storage f is returned as w_i rho0 + (stored deviation) for FP32DEV
+ * and as feq(W) + (stored non-equilibrium part) for FP32NEQ; set_state stores
+ * f minus the same reference (FP32NEQ: feq of the W given, else of the
+ * stored W). */
 int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G);
 int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double *G);
 

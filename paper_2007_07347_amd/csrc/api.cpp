@@ -61,7 +61,7 @@ Layout make_layout(const MeshBuild &mb, int precision)
     Layout L;
     L.np = ((size_t)mb.nc + 63) / 64 * 64;
     if (L.np % 2048 == 0) L.np += 64;
-    const bool dev = precision == SDUGKS_FP32DEV;
+    const bool dev = precision != SDUGKS_FP64;
     const size_t row = L.np * sizeof(double), rowf = L.np * (dev ? sizeof(float) : sizeof(double));
     size_t p = 0;
     auto take = [&](size_t bytes) { size_t o = p; p += align_up(bytes); return o; };
@@ -141,13 +141,13 @@ struct sdugks_s {
         return s;
     }
     DevState state() const { return state_at(cur); }
-    bool dev32() const { return precision == SDUGKS_FP32DEV; }
+    bool dev32() const { return precision != SDUGKS_FP64; }   // f stored as the FP32 deviation
     DevScratch scratch() const { return {at<double>(L.off_fbp), at<double>(L.off_sg)}; }
 };
 
-// Members of one launch: same face class (three or four slots) and storage.
+// Members of one launch: same face class (three or four slots) and precision mode.
 struct BatchGroup {
-    int D = 4, dev32 = 0, block = 64;
+    int D = 4, mode = 0, block = 64;
     size_t lds = 0;
     int n_inst = 0, n_tiles = 0, cap_inst = 0, cap_tiles = 0;
     BatchInst *d_inst = nullptr;      // device table, capacity cap_inst
@@ -180,8 +180,8 @@ namespace {
 int check_prm(const sdugks_params *prm)
 {
     if (!prm) return fail(SDUGKS_EINVAL, "null params");
-    if (prm->precision != SDUGKS_FP64 && prm->precision != SDUGKS_FP32DEV)
-        return fail(SDUGKS_EINVAL, "precision must be SDUGKS_FP64 or SDUGKS_FP32DEV");
+    if (prm->precision != SDUGKS_FP64 && prm->precision != SDUGKS_FP32DEV && prm->precision != SDUGKS_FP32NEQ)
+        return fail(SDUGKS_EINVAL, "precision must be SDUGKS_FP64, SDUGKS_FP32DEV or SDUGKS_FP32NEQ");
     if (prm->macro_flux != SDUGKS_MACRO_CURRENT && prm->macro_flux != SDUGKS_MACRO_LAGGED)
         return fail(SDUGKS_EINVAL, "macro_flux must be SDUGKS_MACRO_CURRENT or SDUGKS_MACRO_LAGGED");
     if (prm->scheme != SDUGKS_SCHEME_SIMPLIFIED && prm->scheme != SDUGKS_SCHEME_ORIGINAL)
@@ -201,8 +201,8 @@ int build(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdug
     std::string err;
     rc = build_mesh(mesh, bc, n_bc, prm, mb, err);
     if (rc) return fail(rc, "mesh: " + err);
-    if (prm->precision == SDUGKS_FP32DEV && mb.n_tiles == 0)
-        return fail(SDUGKS_EINVAL, "SDUGKS_FP32DEV needs the fused step (polygons of at most four faces, at most 64 boundary-condition entries, tile_cells >= 0)");
+    if (prm->precision != SDUGKS_FP64 && mb.n_tiles == 0)
+        return fail(SDUGKS_EINVAL, "FP32 storage needs the fused step (polygons of at most four faces, at most 64 boundary-condition entries, tile_cells >= 0)");
     if (prm->scheme == SDUGKS_SCHEME_ORIGINAL && mb.n_tiles == 0)
         return fail(SDUGKS_EINVAL, "SDUGKS_SCHEME_ORIGINAL needs the fused step (polygons of at most four faces, at most 64 boundary-condition entries, tile_cells >= 0)");
     return SDUGKS_OK;
@@ -253,7 +253,7 @@ int launch_step_at(sdugks_t *h, int c, hipStream_t st)
     DevState s = h->state_at(c);
     const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
     if (h->mb.n_tiles > 0) {
-        HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->dev32(), h->block, st));
+        HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->precision, h->block, st));
     } else {
         DevScratch x = h->scratch();
         HIPCHK(launch_grad(h->dm, s, x, st));
@@ -576,11 +576,15 @@ int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double
     if (!h) return fail(SDUGKS_EINVAL, "null handle");
     HIPCHK(hipSetDevice(h->device));
     const size_t nc = h->mb.nc, np = h->L.np;
-    std::vector<double> ft;
-    if (f && h->scheme == SDUGKS_SCHEME_ORIGINAL) {
-        std::vector<double> Wc(3 * nc);
+    std::vector<double> ft, Wc;
+    const bool neq = h->precision == SDUGKS_FP32NEQ;
+    if (f && (h->scheme == SDUGKS_SCHEME_ORIGINAL || neq)) {
+        // the macros that go with f: the new ones, else the stored ones
+        Wc.resize(3 * nc);
         if (W) std::copy(W, W + 3 * nc, Wc.begin());
         else if (int r0 = sdugks_get_state(h, nullptr, Wc.data(), nullptr)) return r0;
+    }
+    if (f && h->scheme == SDUGKS_SCHEME_ORIGINAL) {
         ft.assign(f, f + 9 * nc);
         tilde_convert(ft.data(), Wc.data(), nc, h->mb.dt / (2.0 * h->mb.tau), false);
         f = ft.data();
@@ -599,12 +603,19 @@ int sdugks_set_state(sdugks_t *h, const double *f, const double *W, const double
     };
     int rc;
     if (f && h->dev32()) {
-        // deviation form: store f - w_i rho0 in FP32
+        // FP32 storage: f - w_i rho0 (FP32DEV) or f - feq(W) (FP32NEQ)
         static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
         std::vector<float> b32(9 * np, 0.0f);
         for (size_t k = 0; k < nc; k++) {
             size_t c = h->mb.perm[k];
-            for (int i = 0; i < 9; i++) b32[i * np + k] = (float)(f[c * 9 + i] - w[i] * h->rho0);
+            for (int i = 0; i < 9; i++) {
+                double ref = w[i] * h->rho0;
+                if (neq) {
+                    const double r = Wc[3 * c];
+                    ref = feq_host(i, r, Wc[3 * c + 1] / r, Wc[3 * c + 2] / r);
+                }
+                b32[i * np + k] = (float)(f[c * 9 + i] - ref);
+            }
         }
         HIPCHK(hipMemcpyAsync(h->base + L.off_f[h->cur], b32.data(), 9 * np * sizeof(float), hipMemcpyHostToDevice, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
@@ -646,24 +657,34 @@ int sdugks_get_state(sdugks_t *h, double *f, double *W, double *G)
         return SDUGKS_OK;
     };
     int rc;
+    const bool neq = h->precision == SDUGKS_FP32NEQ;
+    std::vector<double> Wc;
+    if (f && (neq || h->scheme == SDUGKS_SCHEME_ORIGINAL)) {
+        Wc.resize(3 * nc);
+        if ((rc = get(Wc.data(), 3, L.off_W[h->cur]))) return rc;
+    }
     if (f && h->dev32()) {
+        // FP32 storage: f = w_i rho0 (FP32DEV) or feq(W) (FP32NEQ) + stored part
         static const double w[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
         std::vector<float> b32(9 * np);
         HIPCHK(hipMemcpyAsync(b32.data(), h->base + L.off_f[h->cur], 9 * np * sizeof(float), hipMemcpyDeviceToHost, h->stream));
         HIPCHK(hipStreamSynchronize(h->stream));
         for (size_t k = 0; k < nc; k++) {
             size_t c = h->mb.perm[k];
-            for (int i = 0; i < 9; i++) f[c * 9 + i] = w[i] * h->rho0 + (double)b32[i * np + k];
+            for (int i = 0; i < 9; i++) {
+                double ref = w[i] * h->rho0;
+                if (neq) {
+                    const double r = Wc[3 * c];
+                    ref = feq_host(i, r, Wc[3 * c + 1] / r, Wc[3 * c + 2] / r);
+                }
+                f[c * 9 + i] = ref + (double)b32[i * np + k];
+            }
         }
     } else if (f && (rc = get(f, 9, L.off_f[h->cur]))) {
         return rc;
     }
     if (W && (rc = get(W, 3, L.off_W[h->cur]))) return rc;
-    if (f && h->scheme == SDUGKS_SCHEME_ORIGINAL) {
-        std::vector<double> Wc(3 * nc);
-        if ((rc = get(Wc.data(), 3, L.off_W[h->cur]))) return rc;
-        tilde_convert(f, Wc.data(), nc, h->mb.dt / (2.0 * h->mb.tau), true);
-    }
+    if (f && h->scheme == SDUGKS_SCHEME_ORIGINAL) tilde_convert(f, Wc.data(), nc, h->mb.dt / (2.0 * h->mb.tau), true);
     if (G) {
         if (h->macro == SDUGKS_MACRO_LAGGED) { if ((rc = get(G, 3, L.off_G[h->cur]))) return rc; }
         else std::fill(G, G + 3 * nc, 0.0);
@@ -693,7 +714,8 @@ int sdugks_set_macros(sdugks_t *h, const double *rho, const double *u, const dou
     if (rc) return rc;
     const bool dev = h->dev32();
     HIPCHK(launch_set_equilibrium((int)nc, (int)np, stage, dev ? nullptr : h->at<double>(h->L.off_f[h->cur]),
-                                  dev ? h->at<float>(h->L.off_f[h->cur]) : nullptr, h->rho0,
+                                  dev ? h->at<float>(h->L.off_f[h->cur]) : nullptr,
+                                  h->precision == SDUGKS_FP32NEQ ? -1.0 : h->rho0,
                                   h->at<double>(h->L.off_W[h->cur]), h->at<double>(h->L.off_G[h->cur]),
                                   h->at<double>(h->L.off_snap), h->stream));
     rc = sync_check(h);
@@ -775,7 +797,7 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
         const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
         HIPCHK(hipEventRecord(ev[0], h->stream));
         if (tiled) {
-            HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->dev32(), h->block, h->stream));
+            HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->precision, h->block, h->stream));
             HIPCHK(hipEventRecord(ev[1], h->stream));
         } else {
             DevScratch x = h->scratch();
@@ -828,7 +850,7 @@ int sdugks_boundary_flux(sdugks_t *h, int32_t tag, double *faces, double *sum, i
     if (!h) return fail(SDUGKS_EINVAL, "null handle");
     if (tag >= (int32_t)h->mb.bcs.size()) return fail(SDUGKS_EINVAL, "tag beyond the boundary-condition table");
     HIPCHK(hipSetDevice(h->device));
-    HIPCHK(launch_boundary_flux(h->dm, h->state(), h->bq, h->dev32(), tag, h->stream));
+    HIPCHK(launch_boundary_flux(h->dm, h->state(), h->bq, h->precision, tag, h->stream));
     if (faces && h->bq.n > 0)
         HIPCHK(hipMemcpyAsync(faces, h->bq.out, (size_t)h->bq.n * 4 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipMemcpyAsync(h->host4, h->bq.sum, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -912,20 +934,20 @@ int batch_build_tables(sdugks_batch_t *b)
     std::vector<BatchGroup> want;
     for (size_t k = 0; k < b->members.size(); k++) {
         sdugks_t *h = b->members[k];
-        const int D = h->mb.D <= 3 ? 3 : 4, dev = h->dev32();
+        const int D = h->mb.D <= 3 ? 3 : 4, mode = h->precision;
         BatchGroup *g = nullptr;
-        for (auto &x : want) if (x.D == D && x.dev32 == dev) g = &x;
-        if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->dev32 = dev; }
+        for (auto &x : want) if (x.D == D && x.mode == mode) g = &x;
+        if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->mode = mode; }
         g->members.push_back((int)k);
         g->block = std::max(g->block, h->block);
-        g->lds = std::max(g->lds, step_tiled_lds_bytes(h->dt, dev, (int)h->mb.bcs.size()));
+        g->lds = std::max(g->lds, step_tiled_lds_bytes(h->dt, mode, (int)h->mb.bcs.size()));
         g->n_inst++;
         g->n_tiles += h->mb.n_tiles;
     }
     bool reuse = want.size() == b->groups.size();
     for (size_t k = 0; reuse && k < want.size(); k++) {
         const BatchGroup &o = b->groups[k], &n = want[k];
-        reuse = o.D == n.D && o.dev32 == n.dev32 && o.block >= n.block && o.lds >= n.lds &&
+        reuse = o.D == n.D && o.mode == n.mode && o.block >= n.block && o.lds >= n.lds &&
                 o.cap_inst >= n.n_inst && o.cap_tiles >= n.n_tiles;
     }
     if (!reuse) {
@@ -1013,7 +1035,7 @@ int batch_launch(sdugks_batch_t *b, int parity)
 {
     for (auto &g : b->groups) {
         BatchTable tab{g.d_inst, g.d_tmap};
-        HIPCHK(launch_step_batch(tab, g.D, g.dev32, parity, g.cap_tiles, g.lds, g.block, b->stream));
+        HIPCHK(launch_step_batch(tab, g.D, g.mode, parity, g.cap_tiles, g.lds, g.block, b->stream));
     }
     return SDUGKS_OK;
 }

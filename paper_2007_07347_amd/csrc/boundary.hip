@@ -18,7 +18,9 @@ namespace sdg {
 
 namespace {
 
-__device__ void load_cell(const DevMesh &m, const DevState &s, int dev32, int c, double *f, double &r, double &ux,
+// f of cell c in FP64 whatever the storage (mode: 0 FP64 f; 1 FP32 f - w_i
+// rho0; 2 FP32 f - feq(W)), and its macros.
+__device__ void load_cell(const DevMesh &m, const DevState &s, int mode, int c, double *f, double &r, double &ux,
                           double &uy)
 {
     const int np = m.np;
@@ -26,8 +28,11 @@ __device__ void load_cell(const DevMesh &m, const DevState &s, int dev32, int c,
     ux = s.W[np + c] / r;
     uy = s.W[2 * np + c] / r;
 #pragma unroll
-    for (int i = 0; i < 9; i++)
-        f[i] = dev32 ? (double)s.f32[(size_t)i * np + c] + kW[i] * m.rho0 : s.f[(size_t)i * np + c];
+    for (int i = 0; i < 9; i++) {
+        if (mode == 0) f[i] = s.f[(size_t)i * np + c];
+        else if (mode == 1) f[i] = (double)s.f32[(size_t)i * np + c] + kW[i] * m.rho0;
+        else f[i] = (double)s.f32[(size_t)i * np + c] + feq_one(kW[i], kEx[i], kEy[i], r, ux, uy);
+    }
 }
 
 // Boundary state (rho_b, u_b) of a table entry seen from a cell with macros (r, ux, uy).
@@ -42,14 +47,14 @@ __device__ void bstate(const DevBC &bc, double r, double ux, double uy, double &
     else { rb = r; ub = bc.u; vb = bc.v; }                            // wall
 }
 
-__global__ void __launch_bounds__(64) k_boundary_flux(DevMesh m, DevState s, DevBnd q, int dev32)
+__global__ void __launch_bounds__(64) k_boundary_flux(DevMesh m, DevState s, DevBnd q, int mode)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= q.n) return;
     const int4 h = q.hdr[b];
     const int c = h.x, tag = h.z, D = m.D;
     double fc[9], r, ux, uy;
-    load_cell(m, s, dev32, c, fc, r, ux, uy);
+    load_cell(m, s, mode, c, fc, r, ux, uy);
     double fe[9], fbp[9], sx[9], sy[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
@@ -65,7 +70,7 @@ __global__ void __launch_bounds__(64) k_boundary_flux(DevMesh m, DevState s, Dev
         const double2 w = q.w[(size_t)b * D + j];
         if (v >= 0) {
             double fk[9], rk, uk, vk;
-            load_cell(m, s, dev32, v, fk, rk, uk, vk);
+            load_cell(m, s, mode, v, fk, rk, uk, vk);
 #pragma unroll
             for (int i = 0; i < 9; i++) {
                 const double d = (m.a * fk[i] + m.b * feq_one(kW[i], kEx[i], kEy[i], rk, uk, vk)) - fbp[i];
@@ -141,10 +146,10 @@ __global__ void __launch_bounds__(256) k_boundary_sum(DevBnd q, int tag)
 
 }  // namespace
 
-hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBnd &q, int dev32, int tag, hipStream_t st)
+hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBnd &q, int mode, int tag, hipStream_t st)
 {
     if (q.n > 0) {
-        hipLaunchKernelGGL(k_boundary_flux, dim3((unsigned)((q.n + 63) / 64)), dim3(64), 0, st, m, s, q, dev32);
+        hipLaunchKernelGGL(k_boundary_flux, dim3((unsigned)((q.n + 63) / 64)), dim3(64), 0, st, m, s, q, mode);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

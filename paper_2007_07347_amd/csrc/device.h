@@ -104,20 +104,22 @@ struct DevScratch {
 hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st);
 hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st);
 // Fused one-kernel step over tiles (D <= 4 slots per cell).
-hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
+// mode: 0 FP64; 1 FP32 storage of f - w_i rho0, FP32 face arithmetic; 2 FP32
+// storage of f - feq(W), FP64 arithmetic.
+hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int mode,
                              int block, hipStream_t st);
-size_t step_tiled_lds_bytes(const DevTiles &t, int dev32, int n_bc);
-// Batched fused step over the tiles of all members (same D class and storage).
-hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity, int cap_tiles, size_t lds,
+size_t step_tiled_lds_bytes(const DevTiles &t, int mode, int n_bc);
+// Batched fused step over the tiles of all members (same D class and mode).
+hipError_t launch_step_batch(const BatchTable &tab, int D, int mode, int parity, int cap_tiles, size_t lds,
                              int block, hipStream_t st);
 // Deterministic reductions of the residual / mass / finiteness check: writes
 // out4 = {sum |u-u_snap|^2, sum |u_snap|^2, sum V rho, count of non-finite}.
 // snap = [2][np] (U, V); update_snap re-snapshots.
 hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int update_snap, double *partials,
                          double *out4, hipStream_t st);
-// Boundary face fluxes on the state s (FP64 f, or the deviation form when
-// dev32), then their sums over the faces of `tag` (all when tag < 0).
-hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBnd &q, int dev32, int tag, hipStream_t st);
+// Boundary face fluxes on the state s (mode: the storage of f, as for the
+// step), then their sums over the faces of `tag` (all when tag < 0).
+hipError_t launch_boundary_flux(const DevMesh &m, const DevState &s, const DevBnd &q, int mode, int tag, hipStream_t st);
 // One member of a batched residual: its cells, current W, areas, snapshot
 // (re-snapshotted) and its own partial sums.
 struct ReduceJob {
@@ -130,7 +132,8 @@ struct ReduceJob {
 // Residuals of n members at once: out [n][4] as launch_reduce's out4 each.
 hipError_t launch_reduce_batch(const ReduceJob *jobs, int n, double *out, hipStream_t st);
 // f = feq of the macros m3 = [3][np] (rho, u, v) (FP64 f, or with f32 the
-// FP32 deviation from w_i rho0), W, G = 0 and the residual snapshot.
+// FP32 deviation from w_i rho0, or zero -- the non-equilibrium part -- when
+// rho0 < 0), W, G = 0 and the residual snapshot.
 hipError_t launch_set_equilibrium(int nc, int np, const double *m3, double *f, float *f32, double rho0, double *W,
                                   double *G, double *snap, hipStream_t st);
 // *p = NaN, p pointing at a double (bytes 8) or a float (bytes 4): failure injection.

@@ -219,7 +219,8 @@ __global__ void __launch_bounds__(256) k_reduce_final_batch(const ReduceJob *job
 
 // Equilibrium state from per-cell macros m3 = [3][np] (rho, u, v): f = feq
 // (Eq. Feq; its moments are the macros, Eq. Macro), stored as f or, with f32,
-// as the deviation feq - w_i rho0 in FP32; W = (rho, rho u, rho v); G = 0;
+// as the deviation feq - w_i rho0 in FP32 (rho0 < 0: the non-equilibrium
+// part, zero); W = (rho, rho u, rho v); G = 0;
 // the residual snapshot = the velocity of W.
 __global__ void __launch_bounds__(256) k_set_equilibrium(int nc, int np, const double *m3, double *f, float *f32,
                                                         double rho0, double *W, double *G, double *snap)
@@ -230,7 +231,7 @@ __global__ void __launch_bounds__(256) k_set_equilibrium(int nc, int np, const d
 #pragma unroll
     for (int i = 0; i < 9; i++) {
         const double fe = feq_one(kW[i], kEx[i], kEy[i], r, ux, uy);
-        if (f32) f32[(size_t)i * np + c] = (float)(fe - kW[i] * rho0);
+        if (f32) f32[(size_t)i * np + c] = rho0 < 0.0 ? 0.0f : (float)(fe - kW[i] * rho0);
         else f[(size_t)i * np + c] = fe;
     }
     const double mx = r * ux, my = r * uy;

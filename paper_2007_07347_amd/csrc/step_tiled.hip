@@ -19,12 +19,17 @@
 //            fixed order; then W^{n+1} (Eq. MacroUpdate), feq^{n+1} and
 //            f^{n+1} (Eq. fn+1), each lane writing two or three velocities.
 //
-// Two storage forms share the code: FP64 f, or (DEV) the deviation
-// f - w_i rho0 in FP32 with FP32 face records, gradients and face fluxes
-// computed on deviations (the constant parts cancel exactly: sum_i w_i e_i = 0
-// and the scaled normals of a closed cell sum to zero), per-cell flux sums
-// compensated (TwoSum), and W, its update, feq and the macroscopic fluxes in
-// FP64.
+// Three forms share the code (template parameter PM), all with FP64 density
+// and momentum, their update and the macroscopic fluxes:
+//   PM = 0  f stored and computed in FP64;
+//   PM = 1  the deviation f - w_i rho0 stored in FP32 with FP32 face records
+//           and least-squares weights, fbar+, gradients and face fluxes
+//           computed in FP32 on deviations (the constant parts cancel
+//           exactly: sum_i w_i e_i = 0 and the scaled normals of a closed cell
+//           sum to zero), per-cell flux sums compensated (TwoSum);
+//   PM = 2  the non-equilibrium part f - feq(W) stored in FP32 (FP32 tables),
+//           every operation in FP64: f = feq(W) + stored part on load, and
+//           f^{n+1} - feq(W^{n+1}) rounded to FP32 on store.
 //
 // Every global input of phases 2 and 3 (adjacency, least-squares weights,
 // face records) is requested at kernel start, so its latency overlaps phase 1.
@@ -225,10 +230,13 @@ __device__ __forceinline__ void gradient_cell(const R *sfbp, R *ssg, const doubl
 }
 
 // One time step of tile t of one instance (the whole workgroup takes part).
-template <int D, bool DEV>
+template <int D, int PM>
 __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, const DevState &s, int lagged, int t)
 {
-    using R = typename std::conditional<DEV, float, double>::type;   // storage / face arithmetic
+    constexpr bool S32 = PM != 0;    // f and the tables stored in FP32
+    constexpr bool DEV = PM == 1;    // FP32 arithmetic on deviations from the rest state w_i rho0
+    constexpr bool NEQ = PM == 2;    // stored: f - feq(W); arithmetic in FP64
+    using R = typename std::conditional<DEV, float, double>::type;   // arithmetic of fbar+, gradients, faces
     extern __shared__ double smem[];
     const int P = tl.nl_max, P1 = tl.na_max, PT = tl.nt_max;
     const int np = m.np;
@@ -248,9 +256,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     double *sbc = smem + (((3 * P1 + 2 * PT) * 8 + (9 * P + SG * P1) * (int)sizeof(R) + 15) / 16 * 16) / 8;
     const gmem<int16_t> *ladj = gin(tl.ladj + (size_t)t * D * P1);
     const gmem<int16_t> *lfc = gin(tl.lfc + (size_t)t * D * PT);
-    using R2 = typename std::conditional<DEV, float2, double2>::type;
-    const gmem<R2> *lw, *frt;
-    if constexpr (DEV) {
+    using T2 = typename std::conditional<S32, float2, double2>::type;   // tables
+    const gmem<T2> *lw, *frt;
+    if constexpr (S32) {
         lw = gin(tl.lw32 + (size_t)t * D * P1);
         frt = gin(tl.fr32 + (size_t)t * tl.nf_max * 3);
     } else {
@@ -288,9 +296,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
 #pragma unroll
     for (int sl = 0; sl < D; sl++) {
         la2[sl] = ladj[sl * P1 + t2];
-        const R2 w = lw[sl * P1 + t2];
-        wx2[sl] = w.x;
-        wy2[sl] = w.y;
+        const T2 w = lw[sl * P1 + t2];
+        wx2[sl] = (R)w.x;
+        wy2[sl] = (R)w.y;
     }
     const int a3 = ladj[sl3c * P1 + lc3c];
     const bool pb = tid < m.n_bc;
@@ -300,7 +308,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     R fv[9];
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-        if constexpr (DEV) fv[i] = gin(s.f32)[(size_t)i * np + g1];
+        if constexpr (S32) fv[i] = gin(s.f32)[(size_t)i * np + g1];
         else fv[i] = gin(s.f)[(size_t)i * np + g1];
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -316,11 +324,11 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // the lane's face: the record as seen from the lane's cell (l n, r_self,
     // r_other), or from the other cell (-l n, r_other, r_self)
     const int rec = fc3 >= 0 ? fc3 >> 1 : 0;
-    const R2 lnv = frt[rec], rav = frt[PF + rec], rbv = frt[2 * PF + rec];
+    const T2 lnv = frt[rec], rav = frt[PF + rec], rbv = frt[2 * PF + rec];
     const bool flip = (fc3 & 1) != 0;
-    const R lnx = flip ? -lnv.x : lnv.x, lny = flip ? -lnv.y : lnv.y;
-    const R rsx = flip ? rbv.x : rav.x, rsy = flip ? rbv.y : rav.y;
-    const R rox = flip ? rav.x : rbv.x, roy = flip ? rav.y : rbv.y;
+    const R lnx = flip ? -(R)lnv.x : (R)lnv.x, lny = flip ? -(R)lnv.y : (R)lnv.y;
+    const R rsx = (R)(flip ? rbv.x : rav.x), rsy = (R)(flip ? rbv.y : rav.y);
+    const R rox = (R)(flip ? rav.x : rbv.x), roy = (R)(flip ? rav.y : rbv.y);
 
     // ---- phase 1: macros and fbar+ of every local cell
     if (pb) {
@@ -344,7 +352,9 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         static_for<9>([&](auto I) {
             constexpr int i = I;
             const double fe = feq_c<cEx[i], cEy[i]>(cW[i], r, ux, uy, uu) - (DEV ? cW[i] * m.rho0 : 0.0);
-            sfbp[tid * 9 + i] = ra * fv[i] + rb_ * (R)fe;
+            // NEQ: fv is f - feq, and a + b = 1 (both schemes)
+            if constexpr (NEQ) sfbp[tid * 9 + i] = fe + ra * fv[i];
+            else sfbp[tid * 9 + i] = ra * fv[i] + rb_ * (R)fe;
         });
     }
     __syncthreads();
@@ -361,7 +371,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     // the lane's velocities in the update: sl3, sl3 + 4 and, on lane 0, 8
     // (the tile's own cells, just read in phase 1: cache hits)
     double fo0, fo1, fo2;
-    if constexpr (DEV) {
+    if constexpr (S32) {
         fo0 = gin(s.f32)[(size_t)sl3 * np + g3];
         fo1 = gin(s.f32)[(size_t)(sl3 + 4) * np + g3];
         fo2 = gin(s.f32)[(size_t)8 * np + g3];
@@ -437,7 +447,7 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
     }
 #pragma unroll
     for (int i = 0; i < 9; i++) {
-        if constexpr (DEV) phi[i] = lane_sum4_comp(phi[i]);
+        if constexpr (PM == 1) phi[i] = lane_sum4_comp(phi[i]);
         else phi[i] = lane_sum4(phi[i]);
     }
     g0s = lane_sum4(g0s);
@@ -470,10 +480,20 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
         const double F1 = sl3 == 0 ? phi[4] : (sl3 == 1 ? phi[5] : (sl3 == 2 ? phi[6] : phi[7]));
         const double base = 1.0 - 1.5 * uun;
         const int i0 = sl3, i1 = sl3 + 4;
+        if constexpr (NEQ) {
+            // f^n of this lane's velocities = feq(W^n) + the stored part
+            const double ro = sW[lc], uo = sW[P1 + lc], vo = sW[2 * P1 + lc];
+            const double bo = 1.0 - 1.5 * (uo * uo + vo * vo);
+            const double e0 = sl3 == 0 ? 0.0 : (sl3 == 1 ? uo : (sl3 == 2 ? vo : -uo));
+            const double e1 = sl3 == 0 ? -vo : (sl3 == 1 ? uo + vo : (sl3 == 2 ? vo - uo : -(uo + vo)));
+            fo0 += w0 * ro * (bo + e0 * (3.0 + 4.5 * e0));
+            fo1 += w1 * ro * (bo + e1 * (3.0 + 4.5 * e1));
+            if (sl3 == 0) fo2 += feq_c<cEx[8], cEy[8]>(cW[8], ro, uo, vo, uo * uo + vo * vo);
+        }
+        const double fe0 = w0 * rn * (base + eu0 * (3.0 + 4.5 * eu0)) - (DEV ? w0 * m.rho0 : 0.0);
+        const double fe1 = w1 * rn * (base + eu1 * (3.0 + 4.5 * eu1)) - (DEV ? w1 * m.rho0 : 0.0);
         double v0, v1;
         if (m.scheme == 0) {
-            const double fe0 = w0 * rn * (base + eu0 * (3.0 + 4.5 * eu0)) - (DEV ? w0 * m.rho0 : 0.0);
-            const double fe1 = w1 * rn * (base + eu1 * (3.0 + 4.5 * eu1)) - (DEV ? w1 * m.rho0 : 0.0);
             v0 = (fo0 - dtv * F0 + lam * fe0) * inv;
             v1 = (fo1 - dtv * F1 + lam * fe1) * inv;
         } else {
@@ -481,17 +501,19 @@ __device__ __forceinline__ void step_tile(const DevMesh &m, const DevTiles &tl, 
             v0 = (4.0 / 3.0) * (double)sfbp[lc * 9 + i0] - (1.0 / 3.0) * fo0 - dtv * F0;
             v1 = (4.0 / 3.0) * (double)sfbp[lc * 9 + i1] - (1.0 / 3.0) * fo1 - dtv * F1;
         }
-        if constexpr (DEV) { gout(s.fo32)[(size_t)i0 * np + g] = (float)v0; gout(s.fo32)[(size_t)i1 * np + g] = (float)v1; }
+        if constexpr (NEQ) { v0 -= fe0; v1 -= fe1; }          // store f^{n+1} - feq(W^{n+1})
+        if constexpr (S32) { gout(s.fo32)[(size_t)i0 * np + g] = (float)v0; gout(s.fo32)[(size_t)i1 * np + g] = (float)v1; }
         else { gout(s.fo)[(size_t)i0 * np + g] = v0; gout(s.fo)[(size_t)i1 * np + g] = v1; }
         if (sl3 == 0) {
+            const double fe2 = feq_c<cEx[8], cEy[8]>(cW[8], rn, un, vn, uun) - (DEV ? cW[8] * m.rho0 : 0.0);
             double v2;
             if (m.scheme == 0) {
-                const double fe2 = feq_c<cEx[8], cEy[8]>(cW[8], rn, un, vn, uun) - (DEV ? cW[8] * m.rho0 : 0.0);
                 v2 = (fo2 - dtv * (double)phi[8] + lam * fe2) * inv;
             } else {
                 v2 = (4.0 / 3.0) * (double)sfbp[lc * 9 + 8] - (1.0 / 3.0) * fo2 - dtv * (double)phi[8];
             }
-            if constexpr (DEV) gout(s.fo32)[(size_t)8 * np + g] = (float)v2;
+            if constexpr (NEQ) v2 -= fe2;
+            if constexpr (S32) gout(s.fo32)[(size_t)8 * np + g] = (float)v2;
             else gout(s.fo)[(size_t)8 * np + g] = v2;
         }
     }
@@ -509,12 +531,12 @@ __device__ __forceinline__ int xcd_tile(int n)
 // One block per tile: the tile of this block, XCD by XCD in contiguous ranges
 // (xcd_range_start).  It follows from the block index and the grid size
 // alone, so the first requests wait for nothing but the table pointers.
-template <int D, bool DEV>
+template <int D, int PM>
 __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevState s, int lagged)
 {
     const int x = (int)(blockIdx.x % kXcds);
     const int t = xcd_range_start((int)gridDim.x, x) + (int)(blockIdx.x / kXcds);
-    step_tile<D, DEV>(m, tl, s, lagged, t);
+    step_tile<D, PM>(m, tl, s, lagged, t);
 }
 
 // Batched step: the tiles of all instances form one sequence; the grid covers
@@ -525,7 +547,7 @@ __global__ void __launch_bounds__(256) k_step_tiled(DevMesh m, DevTiles tl, DevS
 // memory is reached through global-address-space pointers (gin, gout in
 // step_tile): the members' pointers come from their records, not from
 // kernel arguments.
-template <int D, bool DEV>
+template <int D, int PM>
 __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
 {
     // the slot's (member, tile) as one 8-byte load, so that the tile index
@@ -551,44 +573,54 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchTable tab, int parity)
     s.f32 = reinterpret_cast<const float *>(fi);
     s.fo32 = reinterpret_cast<float *>(fo);
     if (member < 0) return;
-    step_tile<D, DEV>(m, tl, s, in.lagged, tile);
+    step_tile<D, PM>(m, tl, s, in.lagged, tile);
 }
 
 }  // namespace
 
-size_t step_tiled_lds_bytes(const DevTiles &t, int dev32, int n_bc)
+size_t step_tiled_lds_bytes(const DevTiles &t, int mode, int n_bc)
 {
-    return tile_lds_bytes(t.nl_max, t.na_max, t.nt_max, n_bc, dev32 ? sizeof(float) : sizeof(double));
+    return tile_lds_bytes(t.nl_max, t.na_max, t.nt_max, n_bc, mode == 1 ? sizeof(float) : sizeof(double));
 }
 
 static unsigned step_tiled_grid(const DevTiles &t) { return (unsigned)t.n_tiles; }
 
-hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int dev32,
+// mode: 0 FP64, 1 FP32 deviation with FP32 face arithmetic, 2 FP32
+// storage of f - feq(W) with FP64 arithmetic (the SDUGKS_FP64 / FP32DEV / FP32NEQ values)
+hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int mode,
                              int block, hipStream_t st)
 {
-    const size_t lds = step_tiled_lds_bytes(t, dev32, m.n_bc);
+    const size_t lds = step_tiled_lds_bytes(t, mode, m.n_bc);
     const dim3 grid(step_tiled_grid(t)), blk(block);
+#define SDG_TILED(DD, PP) hipLaunchKernelGGL((k_step_tiled<DD, PP>), grid, blk, lds, st, m, t, s, lagged)
     if (m.D <= 3) {
-        if (dev32) hipLaunchKernelGGL((k_step_tiled<3, true>), grid, blk, lds, st, m, t, s, lagged);
-        else hipLaunchKernelGGL((k_step_tiled<3, false>), grid, blk, lds, st, m, t, s, lagged);
+        if (mode == 1) SDG_TILED(3, 1);
+        else if (mode == 2) SDG_TILED(3, 2);
+        else SDG_TILED(3, 0);
     } else {
-        if (dev32) hipLaunchKernelGGL((k_step_tiled<4, true>), grid, blk, lds, st, m, t, s, lagged);
-        else hipLaunchKernelGGL((k_step_tiled<4, false>), grid, blk, lds, st, m, t, s, lagged);
+        if (mode == 1) SDG_TILED(4, 1);
+        else if (mode == 2) SDG_TILED(4, 2);
+        else SDG_TILED(4, 0);
     }
+#undef SDG_TILED
     return hipGetLastError();
 }
 
-hipError_t launch_step_batch(const BatchTable &tab, int D, int dev32, int parity, int cap_tiles, size_t lds,
+hipError_t launch_step_batch(const BatchTable &tab, int D, int mode, int parity, int cap_tiles, size_t lds,
                              int block, hipStream_t st)
 {
     const dim3 grid((unsigned)batch_grid(cap_tiles)), blk(block);
+#define SDG_BATCH(DD, PP) hipLaunchKernelGGL((k_step_batch<DD, PP>), grid, blk, lds, st, tab, parity)
     if (D <= 3) {
-        if (dev32) hipLaunchKernelGGL((k_step_batch<3, true>), grid, blk, lds, st, tab, parity);
-        else hipLaunchKernelGGL((k_step_batch<3, false>), grid, blk, lds, st, tab, parity);
+        if (mode == 1) SDG_BATCH(3, 1);
+        else if (mode == 2) SDG_BATCH(3, 2);
+        else SDG_BATCH(3, 0);
     } else {
-        if (dev32) hipLaunchKernelGGL((k_step_batch<4, true>), grid, blk, lds, st, tab, parity);
-        else hipLaunchKernelGGL((k_step_batch<4, false>), grid, blk, lds, st, tab, parity);
+        if (mode == 1) SDG_BATCH(4, 1);
+        else if (mode == 2) SDG_BATCH(4, 2);
+        else SDG_BATCH(4, 0);
     }
+#undef SDG_BATCH
     return hipGetLastError();
 }
 

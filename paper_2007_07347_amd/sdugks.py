@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsdugks.so")
 
 OK, EINVAL, ENOMEM, EHIP, EDIVERGED, ENODEV = 0, -1, -2, -3, -4, -5
 BC_WALL, BC_INLET, BC_OUTLET, BC_PERIODIC, BC_SYMMETRY = 1, 2, 3, 4, 5
-FP64, FP32DEV = 0, 1
+FP64, FP32DEV, FP32NEQ = 0, 1, 2
 MACRO_LAGGED, MACRO_CURRENT = 0, 1
 SCHEME_SIMPLIFIED, SCHEME_ORIGINAL = 0, 1
 

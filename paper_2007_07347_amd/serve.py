@@ -22,8 +22,9 @@ and one synchronisation per chunk.
 An instance whose residual has stopped falling while still above the
 tolerance (no 20 % gain over `stall_checks` checks) is handed to the
 backend's optional escalate(): the GPU backend continues it from its current
-state in FP64 storage, whose residual floor lies far below the FP32
-deviation form's, when the larger instance fits the remaining budget.
+state with the same FP32 storage and FP64 arithmetic (FP32NEQ), which has
+no such floor (the floor comes from the FP32 face arithmetic), when the new
+instance fits the remaining budget.
 
 Time-to-steady of a request = completion time - arrival time (queueing
 included).  The backend interface keeps the policy testable without a GPU:
@@ -301,7 +302,8 @@ class SequentialServer(Server):
 class GpuBackend:
     """Backend on libsdugks: one solver per request (its device memory a torch
     tensor of sdugks_state_bytes), one batch for all admitted solvers; a
-    stalled FP32-deviation solver is continued by an FP64 one.  create_async()
+    stalled FP32DEV solver is continued by an FP32NEQ one (same storage,
+    FP64 arithmetic).  create_async()
     builds a solver on a worker thread (the library's mesh build and upload
     release the interpreter lock) on a stream of its own, so that neither its
     host work nor its synchronous uploads wait for the running batch."""
@@ -348,7 +350,7 @@ class GpuBackend:
         kw = self._kw(req)
         if kw["precision"] != self.sd.FP32DEV:
             return None
-        kw["precision"] = self.sd.FP64
+        kw["precision"] = self.sd.FP32NEQ
         need = self.sd.state_bytes(req.mesh, req.bcs, **kw)
         if need > room:
             return None

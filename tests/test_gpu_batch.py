@@ -18,7 +18,7 @@ def sd():
 
 
 def members(sd):
-    """Uneven instances: quads and triangles, FP64 and FP32 deviation storage,
+    """Uneven instances: quads and triangles, FP64 and both FP32 storage forms,
     different viscosities, lids and tile schedules."""
     specs = [
         (meshgen.cavity(23), dict(nu=1e-3)),
@@ -28,6 +28,8 @@ def members(sd):
         (meshgen.jittered_periodic_triangles(12, seed=4), dict(nu=4e-3, precision=sd.FP32DEV)),
         (meshgen.couette(4, 32), dict(nu=1e-2, macro=sd.MACRO_LAGGED, cfl=0.3)),
         (meshgen.cylinder_ogrid(40, 12, seed=7, quad_layers=4), dict(nu=2.5e-3, u0=0.1, precision=sd.FP32DEV)),
+        (meshgen.cavity(31), dict(nu=5e-4, precision=sd.FP32NEQ)),
+        (meshgen.cylinder_ogrid(36, 10, seed=9), dict(nu=2.5e-3, u0=0.1, precision=sd.FP32NEQ)),
     ]
     return specs
 

@@ -26,16 +26,17 @@ def say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("prec", ["f64", "fp32dev"])
+@pytest.mark.parametrize("prec", ["f64", "fp32dev", "fp32neq"])
 @pytest.mark.parametrize("scheme", [0, 1])
 def test_set_macros_is_oracle_equilibrium(sd, oracle_mod, prec, scheme):
     """f = feq(rho, u, v) per cell (Eq. Feq), W = (rho, rho u, rho v), G = 0,
     element by element against the oracle's equilibrium: 1e-15 relative in
-    FP64; in FP32 deviation storage the stored deviation is the rounded
-    FP32 value of feq - w_i rho0 (half an FP32 ulp of it, plus FP64 rounding)."""
+    FP64 and in FP32NEQ (its stored non-equilibrium part is zero); in FP32DEV
+    the stored deviation is the rounded FP32 value of feq - w_i rho0 (half an
+    FP32 ulp of it, plus FP64 rounding)."""
     say("set_macros", prec, "scheme", scheme)
     mesh, bcs = meshgen.cavity(23)
-    p = sd.FP64 if prec == "f64" else sd.FP32DEV
+    p = {"f64": sd.FP64, "fp32dev": sd.FP32DEV, "fp32neq": sd.FP32NEQ}[prec]
     g = sd.Solver(mesh, bcs, nu=1e-3, cfl=0.5, precision=p, scheme=scheme)
     rng = np.random.default_rng(5)
     n = g.n_cells
@@ -45,7 +46,7 @@ def test_set_macros_is_oracle_equilibrium(sd, oracle_mod, prec, scheme):
     f, W, G = g.state()
     ref = np.array([oracle_mod.feq(rho[c], u[c], v[c]) for c in range(n)])
     w = oracle_mod.feq(1.0, 0.0, 0.0)
-    if prec == "f64":
+    if prec != "fp32dev":
         assert np.abs(f - ref).max() <= 1e-15 * np.abs(ref).max()
     else:
         dev = ref - w[None, :]
@@ -60,7 +61,7 @@ def test_set_macros_is_oracle_equilibrium(sd, oracle_mod, prec, scheme):
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "fp32dev"])
+@pytest.mark.parametrize("prec", ["f64", "fp32dev", "fp32neq"])
 @pytest.mark.parametrize("case", ["cavity", "couette_two_kernel"])
 def test_graph_replay_is_bitwise_eager(sd, prec, case):
     """sdugks_step replays captured graphs (32 and 2 steps, an odd step alone,
@@ -69,7 +70,7 @@ def test_graph_replay_is_bitwise_eager(sd, prec, case):
     say("graph replay", case, prec)
     if case == "cavity":
         mesh, bcs = meshgen.cavity(40)
-        kw = dict(nu=1e-3, cfl=0.5, precision=sd.FP64 if prec == "f64" else sd.FP32DEV,
+        kw = dict(nu=1e-3, cfl=0.5, precision={"f64": sd.FP64, "fp32dev": sd.FP32DEV, "fp32neq": sd.FP32NEQ}[prec],
                   tile_cells=32, block_threads=128)
     else:
         if prec != "f64":

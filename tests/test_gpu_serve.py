@@ -1,7 +1,8 @@
 """Serving loop on the GPU: requests admitted by HBM budget into one running
 batch give, bit for bit, the result of the same request solved alone for the
 same number of steps; a request whose FP32-deviation residual stalls above
-the tolerance is continued in FP64 and converges."""
+the tolerance is continued with FP64 arithmetic (same FP32 storage) and
+converges."""
 import numpy as np
 import pytest
 
@@ -36,10 +37,11 @@ def test_served_results_equal_alone():
         s.close()
 
 
-def test_stalled_request_continues_in_fp64():
+def test_stalled_request_continues_with_fp64_arithmetic():
     """Cylinder at Re 20 on a coarse O-grid: the deviation form's residual
-    floors above 1e-7, the server continues the request in FP64 storage from
-    its current state, and it converges to the FP64 solution."""
+    floors above 1e-7, the server continues the request from its current state
+    with FP64 arithmetic on the same FP32 storage, and it converges to the
+    FP64 solution."""
     import torch
     assert torch.cuda.is_available()
     from paper_2007_07347_amd import sdugks, serve
