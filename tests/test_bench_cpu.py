@@ -45,10 +45,15 @@ def test_more_than_one_gpu_is_refused():
 
 def test_unknown_section_is_refused():
     """Checked before anything touches the GPU."""
-    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--sections", "fp32dev,nope"],
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--sections", "cavity256,nope"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
-    assert set(_bench().SECTIONS) == {"fp32dev", "batch", "serving", "cylinder", "cylinder200k", "original", "large"}
+    assert set(_bench().SECTIONS) == {"cavity256", "converge", "serving", "cylinder", "cylinder200k", "original",
+                                      "large"}
+
+
+def test_cpu_model_is_named():
+    assert _bench()._cpu_model()
 
 
 @pytest.mark.parametrize("opt", ["--schedule", "--batch-schedule", "--cylinder-schedule"])
