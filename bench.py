@@ -63,11 +63,12 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="headline workload only")
     p.add_argument("--sections", default=",".join(SECTIONS),
                    help="extra sections to run after the headline, comma-separated from " + ",".join(SECTIONS))
-    p.add_argument("--schedule", default="", metavar="T,B",
-                   help="tile cells and threads per workgroup of the headline and FP32 forms instead of the "
-                        "autotuner's pick (for counter runs, where the profiler distorts the autotuner's timings)")
-    p.add_argument("--batch-schedule", default="", metavar="T,B",
-                   help="schedule of every member of the batched form instead of the batch autotuner's pick")
+    p.add_argument("--schedule", default="", metavar="T,B|structured",
+                   help="schedule of the 256 x 256 cavity forms instead of the autotuner's pick: the general step's "
+                        "tile cells and threads per workgroup, or the structured step (for counter runs, where the "
+                        "profiler distorts the autotuner's timings)")
+    p.add_argument("--batch-schedule", default="", metavar="T,B|structured",
+                   help="schedule of every member of the batched headline instead of the batch autotuner's pick")
     p.add_argument("--cylinder-schedule", default="", metavar="T,B",
                    help="schedule of both precisions on the 200,000-triangle cylinder instead of the autotuner's "
                         "picks (for profiled runs)")
@@ -167,9 +168,11 @@ def headline(sdugks, autotune, meshgen, a, precision):
     import torch
     mesh, bcs = meshgen.cavity(256, beta=1.5, U=0.1)
     kw = dict(nu=0.1 / 1000, cfl=0.5, precision=precision)
-    if a.schedule:
+    if a.schedule == "structured":
+        sched = dict(autotune.STRUCTURED)
+    elif a.schedule:
         t, b = (int(x) for x in a.schedule.split(","))
-        sched = {"tile_cells": t, "block_threads": b}
+        sched = {"tile_cells": t, "block_threads": b, "structured": 1}
     else:
         sched, _ = autotune.autotune(mesh, bcs, steps=200, **kw)
     s = sdugks.Solver(mesh, bcs, **sched, **kw)
@@ -225,9 +228,11 @@ def batch_headline(sdugks, autotune, meshgen, a, seed=2026, n_inst=64):
     prec = sdugks.FP32NEQ if a.headline_precision == "fp32neq" else sdugks.FP32DEV
     problems = batch_problems(sdugks, meshgen, seed, n_inst, precision=prec)
     cells = int(sum(len(m["cell_ptr"]) - 1 for m, _, _ in problems))
-    if a.batch_schedule:
+    if a.batch_schedule == "structured":
+        sched, table = dict(autotune.STRUCTURED), []
+    elif a.batch_schedule:
         t, bt = (int(x) for x in a.batch_schedule.split(","))
-        sched, table = {"tile_cells": t, "block_threads": bt}, []
+        sched, table = {"tile_cells": t, "block_threads": bt, "structured": 1}, []
     else:
         sched, table = autotune.autotune_batch(problems)
     solvers = [sdugks.Solver(mesh, bcs, **sched, **kw) for mesh, bcs, kw in problems]
@@ -376,8 +381,7 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
     checks)."""
     import numpy as np
     import torch
-    cases = {"cavity256_re1000": (lambda: meshgen.cavity(256, beta=1.5, U=0.1),
-                                  dict(nu=1e-4, cfl=0.5, tile_cells=32, block_threads=128)),
+    cases = {"cavity256_re1000": (lambda: meshgen.cavity(256, beta=1.5, U=0.1), dict(nu=1e-4, cfl=0.5, structured=2)),
              "cylinder200k_re40": (lambda: meshgen.cylinder_ogrid(400, 250, seed=0),
                                    dict(nu=0.1 / 40, cfl=0.5, u0=0.1, tile_cells=64, block_threads=256))}
     out = {"rule": f"velocity residual below {tol:g}, checked every {interval} steps (FP64); the FP32 storage "
@@ -702,6 +706,8 @@ def main():
         sys.exit(2)
     for opt, v in (("--schedule", a.schedule), ("--batch-schedule", a.batch_schedule),
                    ("--cylinder-schedule", a.cylinder_schedule)):
+        if opt != "--cylinder-schedule" and v == "structured":
+            continue
         if v and not (len(v.split(",")) == 2 and all(x.isdigit() for x in v.split(","))):
             print(f"{opt} takes two integers T,B (got {v!r})", file=sys.stderr)
             sys.exit(2)
@@ -727,13 +733,22 @@ def main():
     k_ms = ms / a.steps
     achieved = ALG_BYTES["fp32dev"] * cells / (k_ms / 1e3) / 1e9
     eps = hb["eps"]
-    roof = {"bound": "hbm", "kernel": "k_step_batch", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+    structured = hb["sched"].get("structured") == 2
+    # the structured step reads no geometry tables: its own compulsory bytes are
+    # the state alone, f and W read and written once (FP32 f: 2 x (36 + 24))
+    own = 2 * (36 + 24)
+    roof = {"bound": "hbm", "kernel": "k_step_batch_cart" if structured else "k_step_batch",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("batch64_fp32dev", hb["sched"]),
             "alg_bytes_per_cell": ALG_BYTES["fp32dev"], "cells_per_launch": cells, "kernel_ms": round(k_ms, 5),
             "working_set_MB": hb["working_set_MB"],
-            "note": "working set above the 256 MB Infinity Cache; achieved = algorithmic bytes per cell x cells "
-                    "per launch / average launch duration (HIP events on the batch stream)"}
+            "note": "working set above the 256 MB Infinity Cache; achieved = algorithmic bytes per cell (the "
+                    "survey's 304 B: state plus stored geometry of a quad) x cells per launch / average launch "
+                    "duration (HIP events on the batch stream)"}
+    if structured:
+        roof["kernel_own_bytes_per_cell"] = own
+        roof["frac_of_own_bytes"] = round(own * cells / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     out = {
         "metric": "MLUPS (D2Q9 cell-updates/s) & %HBM peak; p50/p99 time-to-steady under load",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -747,8 +762,7 @@ def main():
         "per_instance_loop": {"steps": hb["loop_steps"],
                               "mlups": round(cells * hb["loop_steps"] / (hb["loop_ms"] / 1e3) / 1e6, 1),
                               "ms_per_step": round(hb["loop_ms"] / hb["loop_steps"], 4)},
-        "batch_autotune_ms_per_step": {f"{r['tile_cells']}/{r['block_threads']}": (None if r["ms"] is None else
-                                                                                 round(r["ms"], 4))
+        "batch_autotune_ms_per_step": {autotune.label(r): (None if r["ms"] is None else round(r["ms"], 4))
                                        for r in hb["table"]},
     }
     sections = set() if a.no_extra else {x for x in a.sections.split(",") if x}

@@ -119,6 +119,11 @@ typedef struct {
                                      entries always take the two-kernel step) */
     int32_t block_threads;        /* threads per workgroup of the fused step: 64, 128 or 256 (0 = default) */
     int32_t scheme;               /* SDUGKS_SCHEME_SIMPLIFIED (default) or SDUGKS_SCHEME_ORIGINAL */
+    int32_t structured;           /* structured step for tensor-product quad meshes (the cells are the
+                                     rectangles of two coordinate arrays; periodic sides glued row to row
+                                     or column to column): 0 = used when the mesh is one and tile_cells
+                                     is 0, 1 = never, 2 = required (SDUGKS_EINVAL otherwise).  It fixes
+                                     its own tiles (16 x 7 cells, 256 threads) and ignores block_threads */
 } sdugks_params;
 
 typedef struct sdugks_s sdugks_t;
@@ -135,9 +140,11 @@ int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, 
 /* Host-only: how the fused step would tile this mesh.  tile_cells: the tile
  * size used (0 when the two-kernel step is used: polygons with more than four
  * faces, or tile_cells = -1); n_tiles; max_local: largest tile plus both halo
- * rings; max_ring1: largest tile plus its first ring.  Outputs may be NULL. */
+ * rings; max_ring1: largest tile plus its first ring; structured: 1 when the
+ * structured step is used (its tiles are 16 x 7 cells).  Outputs may be NULL. */
 int sdugks_tiling(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
-                  int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1);
+                  int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1,
+                  int32_t *structured);
 
 /* Device bytes a handle for this problem needs (all state, geometry and
  * scratch); the size of a caller workspace.  Host only. */
@@ -153,10 +160,10 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
 
 /* Advance n >= 0 time steps (asynchronous).  Fails with SDUGKS_EDIVERGED once a
  * residual, mass or state call has seen a non-finite value.  Pairs of steps
- * are replayed from hipGraphs captured on first use (32 steps per replay, then
- * 2; an odd last step is launched alone); the graphs are captured on a private
- * stream of the handle and launched on its stream, which may be the null
- * stream.  Results are bitwise those of sdugks_step_eager. */
+ * are replayed from hipGraphs built on first use (32 steps per replay, then
+ * 2; an odd last step is launched alone), node by node rather than by stream
+ * capture, and launched on the handle's stream, which may be the null stream.
+ * Results are bitwise those of sdugks_step_eager. */
 int sdugks_step(sdugks_t *h, int64_t n);
 
 /* The same n steps with one plain kernel launch each (no graph): for callers
@@ -228,11 +235,12 @@ const char *sdugks_last_error(void);
  * all members; members with three-slot and four-slot cells, or with the two
  * storage forms, go to separate launches.  Each XCD takes an equal,
  * contiguous share of the concatenated tile sequence.  Steps are replayed
- * from captured hipGraphs (one of 32 steps, one of 2 for the rest) that read
+ * from hipGraphs built node by node (one of 32 steps, one of 2 for the rest;
+ * no stream capture, so other threads may allocate meanwhile) that read
  * a device-side table (members, and each tile slot's member and local tile),
  * so changing the membership only rewrites the table unless the tile count
- * or the LDS a member needs outgrows what the launch was captured with (it is
- * then re-captured).
+ * or the LDS a member needs outgrows what the launch was built with (it is
+ * then rebuilt).
  *  - members: handles using the fused step (n >= 1, no duplicates, same
  *    device); they keep their own state and stay usable individually, and the
  *    batch does not own them: destroy the batch (or change its membership)

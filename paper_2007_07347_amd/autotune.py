@@ -1,7 +1,10 @@
-"""Autotuner of the fused step's schedule: tile size (cells per workgroup,
-which sets the halo overhead and the LDS per workgroup, hence how many
-workgroups share a compute unit) and threads per workgroup (which sets how
-many lanes serve each cell in every phase).
+"""Autotuner of the fused step's schedule: on tensor-product quad meshes the
+structured step (fixed 16 x 7-cell tiles, one lane per face) against the
+general fused step; for the general step, the tile size (cells per
+workgroup, which sets the halo overhead and the LDS per workgroup, hence how
+many workgroups share a compute unit) and threads per workgroup (which sets
+how many lanes serve each cell in every phase: four per cell, one per face
+of a quad, in the face pass).
 
 Each candidate is built with the library, warmed up, and timed with HIP
 events over a fixed number of steps on the instance's own stream; the
@@ -18,8 +21,27 @@ import numpy as np
 
 from . import sdugks
 
-# (tile cells, threads): a tile holds at most a quarter as many cells as threads
+# (tile cells, threads) of the general step: a tile holds at most a quarter as
+# many cells as threads
 CANDIDATES = [(16, 64), (16, 128), (32, 128), (16, 256), (32, 256), (64, 256)]
+STRUCTURED = {"structured": 2}
+
+
+def label(sched):
+    return "structured" if sched.get("structured") == 2 else f"{sched['tile_cells']}/{sched['block_threads']}"
+
+
+def candidates_for(problems, candidates=None):
+    """Schedules to try: the structured step when every mesh is a tensor
+    product (it takes no tile parameters), then the general step's."""
+    out = []
+    if candidates is None:
+        if all(sdugks.tiling(m, b, **{k: v for k, v in kw.items() if k != "precision"})["structured"]
+               for m, b, kw in problems):
+            out.append(dict(STRUCTURED))
+        candidates = CANDIDATES
+    out += [{"tile_cells": t, "block_threads": b, "structured": 1} for t, b in candidates]
+    return out
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
 
@@ -49,9 +71,9 @@ def _store_cache(path, db):
         pass
 
 
-def time_candidate(mesh, bcs, tile_cells, block_threads, steps=200, warmup=20, **kw):
+def time_candidate(mesh, bcs, sched, steps=200, warmup=20, **kw):
     import torch
-    s = sdugks.Solver(mesh, bcs, tile_cells=tile_cells, block_threads=block_threads, **kw)
+    s = sdugks.Solver(mesh, bcs, **sched, **kw)
     s.step(warmup)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(s.stream)
@@ -71,18 +93,18 @@ def autotune(mesh, bcs, candidates=None, steps=200, cache=CACHE, refresh=False, 
     if not refresh and key in db:
         return db[key]["best"], db[key]["table"]
     table = []
-    for t, b in (candidates or CANDIDATES):
+    for sched in candidates_for([(mesh, bcs, kw)], candidates):
         try:
-            ms = time_candidate(mesh, bcs, t, b, steps=steps, **kw)
+            ms = time_candidate(mesh, bcs, sched, steps=steps, **kw)
         except sdugks.SdugksError as e:        # e.g. a tile too small for the mesh degree
-            table.append({"tile_cells": t, "block_threads": b, "ms": None, "error": str(e)})
+            table.append({**sched, "ms": None, "error": str(e)})
             continue
-        table.append({"tile_cells": t, "block_threads": b, "ms": ms})
+        table.append({**sched, "ms": ms})
     ok = [r for r in table if r["ms"] is not None]
     if not ok:
         raise RuntimeError("no candidate schedule fits: " + "; ".join(r["error"] for r in table))
     best = min(ok, key=lambda r: r["ms"])
-    best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
+    best = {k: v for k, v in best.items() if k not in ("ms", "error")}
     if cache:
         db[key] = {"best": best, "table": table}
         _store_cache(cache, db)
@@ -98,13 +120,13 @@ def batch_signature(problems):
     return f"batch-{len(problems)}-{h.hexdigest()[:12]}"
 
 
-def time_batch_candidate(problems, tile_cells, block_threads, steps=50, warmup=10):
+def time_batch_candidate(problems, sched, steps=50, warmup=10):
     """ms per batched step of all problems, every member on this schedule."""
     import torch
     solvers = []
     try:
         for mesh, bcs, kw in problems:
-            solvers.append(sdugks.Solver(mesh, bcs, tile_cells=tile_cells, block_threads=block_threads, **kw))
+            solvers.append(sdugks.Solver(mesh, bcs, **sched, **kw))
         b = sdugks.Batch(solvers)
         try:
             b.step(warmup)
@@ -133,18 +155,18 @@ def autotune_batch(problems, candidates=None, steps=50, cache=CACHE, refresh=Fal
     if not refresh and key in db:
         return db[key]["best"], db[key]["table"]
     table = []
-    for t, b in (candidates or CANDIDATES):
+    for sched in candidates_for(problems, candidates):
         try:
-            ms = time_batch_candidate(problems, t, b, steps=steps)
+            ms = time_batch_candidate(problems, sched, steps=steps)
         except sdugks.SdugksError as e:
-            table.append({"tile_cells": t, "block_threads": b, "ms": None, "error": str(e)})
+            table.append({**sched, "ms": None, "error": str(e)})
             continue
-        table.append({"tile_cells": t, "block_threads": b, "ms": ms})
+        table.append({**sched, "ms": ms})
     ok = [r for r in table if r["ms"] is not None]
     if not ok:
         raise RuntimeError("no candidate schedule fits: " + "; ".join(r["error"] for r in table))
     best = min(ok, key=lambda r: r["ms"])
-    best = {"tile_cells": best["tile_cells"], "block_threads": best["block_threads"]}
+    best = {k: v for k, v in best.items() if k not in ("ms", "error")}
     if cache:
         db[key] = {"best": best, "table": table}
         _store_cache(cache, db)

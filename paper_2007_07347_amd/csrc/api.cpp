@@ -49,6 +49,7 @@ struct Layout {
     size_t off_part = 0, off_out = 0, total = 0;
     size_t off_thdr = 0, off_lgid = 0, off_ladj = 0, off_lfc = 0, off_frec = 0, off_lw = 0;
     size_t off_bq_hdr = 0, off_bq_nb = 0, off_bq_w = 0, off_bq_geo = 0, off_bq_out = 0, off_bq_sum = 0;
+    size_t off_ccol = 0, off_crow = 0, off_cside = 0;
 };
 
 // What the three step forms need: the two-kernel step keeps fbar+ and its
@@ -70,7 +71,12 @@ Layout make_layout(const MeshBuild &mb, int precision)
         L.off_W[k] = take(3 * row);
         L.off_G[k] = take(3 * row);
     }
-    if (mb.n_tiles > 0) {
+    if (mb.cart) {
+        // structured step: one record per column and per row, the side tags
+        L.off_ccol = take(mb.col.size() * sizeof(double));
+        L.off_crow = take(mb.row.size() * sizeof(double));
+        L.off_cside = take(mb.side.size() * sizeof(int32_t));
+    } else if (mb.n_tiles > 0) {
         // fused step: fbar+ and its gradient live in LDS only
         L.off_thdr = take(mb.tile_hdr.size() * sizeof(int32_t));
         L.off_lgid = take(mb.lgid.size() * sizeof(int32_t));
@@ -121,11 +127,11 @@ struct sdugks_s {
     int block = 256;
     DevMesh dm{};
     DevTiles dt{};
+    DevCart dc{};
     DevBnd bq{};
     double *host4 = nullptr;     // pinned, 4 doubles
-    // steps replayed from captured graphs: [buffer index at launch][one pair,
-    // kGraphPairs pairs], captured on a private stream and launched on `stream`
-    hipStream_t cap_stream = nullptr;
+    // steps replayed from graphs: [buffer index at launch][one pair,
+    // kGraphPairs pairs], launched on `stream`
     hipGraph_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
 
@@ -148,6 +154,7 @@ struct sdugks_s {
 // Members of one launch: same face class (three or four slots) and precision mode.
 struct BatchGroup {
     int D = 4, mode = 0, block = 64;
+    bool cart = false;
     size_t lds = 0;
     int n_inst = 0, n_tiles = 0, cap_inst = 0, cap_tiles = 0;
     BatchInst *d_inst = nullptr;      // device table, capacity cap_inst
@@ -247,17 +254,20 @@ int reduce(sdugks_t *h, int update_snap, double out[4])
     return SDUGKS_OK;
 }
 
-// One step that reads buffer index c, on stream st (no bookkeeping).
-int launch_step_at(sdugks_t *h, int c, hipStream_t st)
+// One step that reads buffer index c, on stream st, or appended to a graph
+// chain (no bookkeeping).
+int launch_step_at(sdugks_t *h, int c, hipStream_t st, GraphChain *gc = nullptr)
 {
     DevState s = h->state_at(c);
     const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
-    if (h->mb.n_tiles > 0) {
-        HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->precision, h->block, st));
+    if (h->mb.cart) {
+        HIPCHK(launch_step_cart(h->dm, h->dc, s, lagged, h->precision, st, gc));
+    } else if (h->mb.n_tiles > 0) {
+        HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->precision, h->block, st, gc));
     } else {
         DevScratch x = h->scratch();
-        HIPCHK(launch_grad(h->dm, s, x, st));
-        HIPCHK(launch_flux_update(h->dm, s, x, lagged, st));
+        HIPCHK(launch_grad(h->dm, s, x, st, gc));
+        HIPCHK(launch_flux_update(h->dm, s, x, lagged, st, gc));
     }
     return SDUGKS_OK;
 }
@@ -282,22 +292,20 @@ void release_step_graphs(sdugks_t *h)
         }
 }
 
-// Capture `pairs` pairs of steps starting from buffer index c into a graph
-// (on the handle's private capture stream; the graph is launched on its
-// stream).
+// `pairs` pairs of steps starting from buffer index c as one graph, built
+// node by node (no stream capture: nothing another thread does can
+// invalidate it); launched on the handle's stream.
 int capture_step_graph(sdugks_t *h, int c, int64_t pairs, hipGraph_t &graph, hipGraphExec_t &exec)
 {
-    if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
-    HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipGraphCreate(&gr, 0));
+    GraphChain gc{gr, nullptr};
     int rc = 0;
     for (int64_t k = 0; k < pairs && !rc; k++) {
-        rc = launch_step_at(h, c, h->cap_stream);
-        if (!rc) rc = launch_step_at(h, c ^ 1, h->cap_stream);
+        rc = launch_step_at(h, c, h->stream, &gc);
+        if (!rc) rc = launch_step_at(h, c ^ 1, h->stream, &gc);
     }
-    hipGraph_t gr = nullptr;
-    const hipError_t e = hipStreamEndCapture(h->cap_stream, &gr);
-    if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
-    if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    if (rc) { hipGraphDestroy(gr); return rc; }
     const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
         hipGraphDestroy(gr);
@@ -336,15 +344,16 @@ int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, 
 }
 
 int sdugks_tiling(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
-                  int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1)
+                  int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1, int32_t *structured)
 {
     MeshBuild mb;
     int rc = build(mesh, bc, n_bc, prm, mb);
     if (rc) return rc;
     if (tile_cells) *tile_cells = mb.tile_T;
     if (n_tiles) *n_tiles = mb.n_tiles;
-    if (max_local) *max_local = mb.nl_max;
-    if (max_ring1) *max_ring1 = mb.na_max;
+    if (max_local) *max_local = mb.cart ? (kCartTX + 4) * (kCartTY + 4) : mb.nl_max;
+    if (max_ring1) *max_ring1 = mb.cart ? (kCartTX + 2) * (kCartTY + 2) : mb.na_max;
+    if (structured) *structured = mb.cart ? 1 : 0;
     return SDUGKS_OK;
 }
 
@@ -483,7 +492,20 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         h->bq.out = h->at<double>(L.off_bq_out);
         h->bq.sum = h->at<double>(L.off_bq_sum);
     }
-    if (tiled) {
+    if (mb.cart) {
+        auto up = [&](size_t off, const void *src, size_t bytes) {
+            return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+        };
+        if (!up(L.off_ccol, mb.col.data(), mb.col.size() * sizeof(double)) ||
+            !up(L.off_crow, mb.row.data(), mb.row.size() * sizeof(double)) ||
+            !up(L.off_cside, mb.side.data(), mb.side.size() * sizeof(int32_t)))
+            return cleanup(fail(SDUGKS_EHIP, "upload of the structured-grid tables failed"));
+        h->dc.nx = mb.nx; h->dc.ny = mb.ny; h->dc.ntx = mb.ntx; h->dc.nty = mb.nty;
+        h->dc.per_x = mb.per_x; h->dc.per_y = mb.per_y;
+        h->dc.col = h->at<double>(L.off_ccol);
+        h->dc.row = h->at<double>(L.off_crow);
+        h->dc.side = h->at<int32_t>(L.off_cside);
+    } else if (tiled) {
         auto up = [&](size_t off, const void *src, size_t bytes) {
             return hipMemcpy(h->base + off, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
         };
@@ -796,7 +818,10 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
         DevState s = h->state();
         const int lagged = h->macro == SDUGKS_MACRO_LAGGED;
         HIPCHK(hipEventRecord(ev[0], h->stream));
-        if (tiled) {
+        if (h->mb.cart) {
+            HIPCHK(launch_step_cart(h->dm, h->dc, s, lagged, h->precision, h->stream));
+            HIPCHK(hipEventRecord(ev[1], h->stream));
+        } else if (tiled) {
             HIPCHK(launch_step_tiled(h->dm, h->dt, s, lagged, h->precision, h->block, h->stream));
             HIPCHK(hipEventRecord(ev[1], h->stream));
         } else {
@@ -816,7 +841,8 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
     }
     for (int k = 0; k < nk; k++) avg_ms[k] = n ? acc[k] / n : 0;
     if (names) {
-        if (tiled) names[0] = "k_step_tiled";
+        if (h->mb.cart) names[0] = "k_step_cart";
+        else if (tiled) names[0] = "k_step_tiled";
         else { names[0] = "k_grad"; names[1] = "k_flux_update"; }
     }
     *n_kernels = nk;
@@ -876,7 +902,6 @@ int sdugks_destroy(sdugks_t *h)
     hipSetDevice(h->device);
     hipStreamSynchronize(h->stream);
     release_step_graphs(h);
-    if (h->cap_stream) hipStreamDestroy(h->cap_stream);
     if (h->own) hipFree(h->base);
     hipHostFree(h->host4);
     delete h;
@@ -935,19 +960,21 @@ int batch_build_tables(sdugks_batch_t *b)
     for (size_t k = 0; k < b->members.size(); k++) {
         sdugks_t *h = b->members[k];
         const int D = h->mb.D <= 3 ? 3 : 4, mode = h->precision;
+        const bool cart = h->mb.cart;
         BatchGroup *g = nullptr;
-        for (auto &x : want) if (x.D == D && x.mode == mode) g = &x;
-        if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->mode = mode; }
+        for (auto &x : want) if (x.D == D && x.mode == mode && x.cart == cart) g = &x;
+        if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->mode = mode; g->cart = cart; }
         g->members.push_back((int)k);
-        g->block = std::max(g->block, h->block);
-        g->lds = std::max(g->lds, step_tiled_lds_bytes(h->dt, mode, (int)h->mb.bcs.size()));
+        g->block = cart ? 256 : std::max(g->block, h->block);
+        g->lds = std::max(g->lds, cart ? step_cart_lds_bytes(mode, (int)h->mb.bcs.size())
+                                       : step_tiled_lds_bytes(h->dt, mode, (int)h->mb.bcs.size()));
         g->n_inst++;
         g->n_tiles += h->mb.n_tiles;
     }
     bool reuse = want.size() == b->groups.size();
     for (size_t k = 0; reuse && k < want.size(); k++) {
         const BatchGroup &o = b->groups[k], &n = want[k];
-        reuse = o.D == n.D && o.mode == n.mode && o.block >= n.block && o.lds >= n.lds &&
+        reuse = o.D == n.D && o.mode == n.mode && o.cart == n.cart && o.block >= n.block && o.lds >= n.lds &&
                 o.cap_inst >= n.n_inst && o.cap_tiles >= n.n_tiles;
     }
     if (!reuse) {
@@ -989,6 +1016,7 @@ int batch_build_tables(sdugks_batch_t *b)
             BatchInst &e = inst[k];
             e.m = h->dm;
             e.t = h->dt;
+            e.c = h->dc;
             for (int p = 0; p < 2; p++) {
                 e.f[p] = h->base + h->L.off_f[p];
                 e.W[p] = h->at<double>(h->L.off_W[p]);
@@ -1031,11 +1059,12 @@ int batch_build(sdugks_batch_t *b)
     return rc;
 }
 
-int batch_launch(sdugks_batch_t *b, int parity)
+int batch_launch(sdugks_batch_t *b, int parity, GraphChain *gc = nullptr)
 {
     for (auto &g : b->groups) {
         BatchTable tab{g.d_inst, g.d_tmap};
-        HIPCHK(launch_step_batch(tab, g.D, g.mode, parity, g.cap_tiles, g.lds, g.block, b->stream));
+        if (g.cart) HIPCHK(launch_step_batch_cart(tab, g.mode, parity, g.cap_tiles, g.lds, b->stream, gc));
+        else HIPCHK(launch_step_batch(tab, g.D, g.mode, parity, g.cap_tiles, g.lds, g.block, b->stream, gc));
     }
     return SDUGKS_OK;
 }
@@ -1113,19 +1142,18 @@ int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_
 
 namespace {
 
-// Capture `pairs` pairs of batched steps on the batch's stream into a graph.
+// `pairs` pairs of batched steps as one graph, built node by node.
 int batch_capture(sdugks_batch_t *b, int64_t pairs, hipGraph_t &graph, hipGraphExec_t &exec)
 {
-    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipGraphCreate(&gr, 0));
+    GraphChain gc{gr, nullptr};
     int rc = 0;
     for (int64_t k = 0; k < pairs && !rc; k++) {
-        rc = batch_launch(b, 0);
-        if (!rc) rc = batch_launch(b, 1);
+        rc = batch_launch(b, 0, &gc);
+        if (!rc) rc = batch_launch(b, 1, &gc);
     }
-    hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamEndCapture(b->stream, &gr);
-    if (rc) { if (gr) hipGraphDestroy(gr); return rc; }
-    if (e != hipSuccess) return fail(SDUGKS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    if (rc) { hipGraphDestroy(gr); return rc; }
     const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
         hipGraphDestroy(gr);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <tuple>
+#include <utility>
 
 namespace sdg {
 
@@ -60,11 +62,22 @@ struct DevTiles {
     const float2 *fr32, *lw32;          // deviation form
 };
 
-// One member of a batched launch: its mesh, tiles, both ping-pong buffers
-// and the buffer index it reads at parity 0.
+// Structured step (tensor-product quad meshes): grid and tile counts,
+// periodic flags, per-column / per-row records [n][kCartVals] and the
+// boundary-condition entry of every boundary face of the four sides (bottom
+// [nx], top [nx], left [ny], right [ny]; -1 on periodic sides).
+struct DevCart {
+    int32_t nx, ny, ntx, nty, per_x, per_y;
+    const double *col, *row;
+    const int32_t *side;
+};
+
+// One member of a batched launch: its mesh, tiles (or structured grid), both
+// ping-pong buffers and the buffer index it reads at parity 0.
 struct BatchInst {
     DevMesh m;
     DevTiles t;
+    DevCart c;
     void *f[2];
     double *W[2];
     double *G[2];
@@ -100,18 +113,66 @@ struct DevScratch {
     double *sg;                         // [18][np] its least-squares gradient (x rows 0..8, y rows 9..17)
 };
 
+// Where a step launcher puts its kernels: on its stream, or, given a chain,
+// as the next nodes of a graph under construction (each node depending on the
+// previous one).  Graphs are built node by node rather than by stream
+// capture, so that another thread's allocations or synchronous copies can
+// never invalidate them.
+struct GraphChain {
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+};
+
+template <typename Tup, size_t... I>
+inline void kernel_arg_ptrs(Tup &t, void **p, std::index_sequence<I...>)
+{
+    ((p[I] = (void *)&std::get<I>(t)), ...);
+}
+
+// Launch fn<<<grid, blk, lds, st>>>(args...), or append it to the chain.
+template <typename... P, typename... A>
+inline hipError_t emit(void (*fn)(P...), dim3 grid, dim3 blk, size_t lds, hipStream_t st, GraphChain *gc,
+                       A &&...args)
+{
+    std::tuple<P...> vals(std::forward<A>(args)...);
+    void *ptrs[sizeof...(P) > 0 ? sizeof...(P) : 1];
+    kernel_arg_ptrs(vals, ptrs, std::index_sequence_for<P...>{});
+    if (!gc) return hipLaunchKernel(reinterpret_cast<const void *>(fn), grid, blk, ptrs, lds, st);
+    hipKernelNodeParams kp{};
+    kp.func = reinterpret_cast<void *>(fn);
+    kp.gridDim = grid;
+    kp.blockDim = blk;
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = ptrs;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, gc->graph, gc->last ? &gc->last : nullptr, gc->last ? 1 : 0, &kp);
+    if (e == hipSuccess) gc->last = node;
+    return e;
+}
+
 // Launchers (stream-ordered, no synchronisation).  Return the hipError_t of the launch.
-hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st);
-hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st);
+hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st,
+                       GraphChain *gc = nullptr);
+hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st,
+                              GraphChain *gc = nullptr);
 // Fused one-kernel step over tiles (D <= 4 slots per cell).
 // mode: 0 FP64; 1 FP32 storage of f - w_i rho0, FP32 face arithmetic; 2 FP32
 // storage of f - feq(W), FP64 arithmetic.
 hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int mode,
-                             int block, hipStream_t st);
+                             int block, hipStream_t st, GraphChain *gc = nullptr);
 size_t step_tiled_lds_bytes(const DevTiles &t, int mode, int n_bc);
+// Structured step over 16 x 7-cell tiles of a tensor-product quad mesh (one
+// workgroup of 256 threads per tile), and its batched form (members of one
+// mode on the structured step).
+hipError_t launch_step_cart(const DevMesh &m, const DevCart &c, const DevState &s, int lagged, int mode,
+                            hipStream_t st, GraphChain *gc = nullptr);
+size_t step_cart_lds_bytes(int mode, int n_bc);
+hipError_t launch_step_batch_cart(const BatchTable &tab, int mode, int parity, int cap_tiles, size_t lds,
+                                  hipStream_t st, GraphChain *gc = nullptr);
 // Batched fused step over the tiles of all members (same D class and mode).
 hipError_t launch_step_batch(const BatchTable &tab, int D, int mode, int parity, int cap_tiles, size_t lds,
-                             int block, hipStream_t st);
+                             int block, hipStream_t st, GraphChain *gc = nullptr);
 // Deterministic reductions of the residual / mass / finiteness check: writes
 // out4 = {sum |u-u_snap|^2, sum |u_snap|^2, sum V rho, count of non-finite}.
 // snap = [2][np] (U, V); update_snap re-snapshots.

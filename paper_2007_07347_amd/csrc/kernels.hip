@@ -254,23 +254,20 @@ __global__ void k_poke_nan(void *p, int bytes)
 
 }  // namespace
 
-hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st)
+hipError_t launch_grad(const DevMesh &m, const DevState &s, const DevScratch &x, hipStream_t st, GraphChain *gc)
 {
-    dim3 grid((m.nc + 255) / 256, 9);
-    hipLaunchKernelGGL(k_grad, grid, dim3(256), 0, st, m, s, x);
-    return hipGetLastError();
+    return emit(&k_grad, dim3((m.nc + 255) / 256, 9), dim3(256), 0, st, gc, m, s, x);
 }
 
-hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st)
+hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScratch &x, int lagged, hipStream_t st,
+                              GraphChain *gc)
 {
     if (m.D <= 4) {
         const long threads = (long)m.nc * 4;
-        hipLaunchKernelGGL(k_flux_update<4>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, m, s, x, lagged);
-    } else {
-        const long threads = (long)m.nc * 8;
-        hipLaunchKernelGGL(k_flux_update<8>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, m, s, x, lagged);
+        return emit(&k_flux_update<4>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, gc, m, s, x, lagged);
     }
-    return hipGetLastError();
+    const long threads = (long)m.nc * 8;
+    return emit(&k_flux_update<8>, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, gc, m, s, x, lagged);
 }
 
 hipError_t launch_reduce(const DevMesh &m, const double *W, double *snap, int update_snap, double *partials,

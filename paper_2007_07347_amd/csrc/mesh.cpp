@@ -433,6 +433,90 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     for (int32_t e = 0; e < m->n_bedges; e++)
         if (bc[bed[e].tag].type == SDUGKS_BC_PERIODIC && !glued[e]) BAD("periodic edge %d left unglued", e);
 
+    // ---- structured (tensor-product) quad meshes: the cells are the
+    // rectangles of two sorted coordinate arrays, every plain boundary face on
+    // one of the four sides, periodic gluing (if any) between opposite sides
+    // of the same row or column
+    bool cart = false;
+    std::vector<int32_t> cart_cell;   // (i + nx j) -> caller cell
+    std::vector<double> cxs, cys;
+    int32_t cnx = 0, cny = 0, cper_x = 0, cper_y = 0;
+    std::vector<int32_t> cside;
+    if (prm->structured < 0 || prm->structured > 2) BAD("structured must be 0, 1 or 2");
+    if (prm->structured != 1 && (prm->structured == 2 || prm->tile_cells == 0) && D == 4 && n_bc <= kMaxTileBcs) {
+        auto detect = [&]() -> bool {
+            for (int32_t c = 0; c < nc; c++)
+                if (m->cell_ptr[c + 1] - m->cell_ptr[c] != 4) return false;
+            for (int32_t v = 0; v < nn; v++) { cxs.push_back(xy[2 * v]); cys.push_back(xy[2 * v + 1]); }
+            std::sort(cxs.begin(), cxs.end());
+            cxs.erase(std::unique(cxs.begin(), cxs.end()), cxs.end());
+            std::sort(cys.begin(), cys.end());
+            cys.erase(std::unique(cys.begin(), cys.end()), cys.end());
+            cnx = (int32_t)cxs.size() - 1;
+            cny = (int32_t)cys.size() - 1;
+            if (cnx < 2 || cny < 2 || (int64_t)cnx * cny != nc) return false;
+            cart_cell.assign((size_t)nc, -1);
+            std::vector<int32_t> ci(nc), cj(nc);
+            for (int32_t c = 0; c < nc; c++) {
+                int32_t ii[4], jj[4], k0 = 0;
+                for (int32_t k = 0; k < 4; k++) {
+                    const int32_t v = m->cell_nodes[m->cell_ptr[c] + k];
+                    ii[k] = (int32_t)(std::lower_bound(cxs.begin(), cxs.end(), xy[2 * v]) - cxs.begin());
+                    jj[k] = (int32_t)(std::lower_bound(cys.begin(), cys.end(), xy[2 * v + 1]) - cys.begin());
+                    if (ii[k] < ii[k0] || (ii[k] == ii[k0] && jj[k] < jj[k0])) k0 = k;
+                }
+                const int32_t i = ii[k0], j = jj[k0];
+                const int32_t di[4] = {0, 1, 1, 0}, dj[4] = {0, 0, 1, 1};   // counter-clockwise from the lower left
+                for (int32_t k = 0; k < 4; k++)
+                    if (ii[(k0 + k) % 4] != i + di[k] || jj[(k0 + k) % 4] != j + dj[k]) return false;
+                if (i >= cnx || j >= cny || cart_cell[i + (size_t)cnx * j] >= 0) return false;
+                cart_cell[i + (size_t)cnx * j] = c;
+                ci[c] = i;
+                cj[c] = j;
+            }
+            cside.assign(2 * (size_t)cnx + 2 * (size_t)cny, -2);
+            int32_t glued_x = 0, glued_y = 0;
+            for (const Face &f : faces) {
+                const int32_t i = ci[f.o], j = cj[f.o];
+                if (f.n < 0) {
+                    if (f.lny == 0 && f.lnx < 0 && i == 0) cside[2 * cnx + j] = f.tag;
+                    else if (f.lny == 0 && f.lnx > 0 && i == cnx - 1) cside[2 * cnx + cny + j] = f.tag;
+                    else if (f.lnx == 0 && f.lny < 0 && j == 0) cside[i] = f.tag;
+                    else if (f.lnx == 0 && f.lny > 0 && j == cny - 1) cside[cnx + i] = f.tag;
+                    else return false;
+                    continue;
+                }
+                const int32_t in = ci[f.n], jn = cj[f.n];
+                if (f.tx == 0 && f.ty == 0) {
+                    if (std::abs(in - i) + std::abs(jn - j) != 1) return false;
+                    continue;
+                }
+                // glued across a periodic pair of sides
+                if (j == jn && f.ty == 0 && ((i == 0 && in == cnx - 1) || (i == cnx - 1 && in == 0))) glued_x++;
+                else if (i == in && f.tx == 0 && ((j == 0 && jn == cny - 1) || (j == cny - 1 && jn == 0))) glued_y++;
+                else return false;
+            }
+            if (glued_x && glued_x != cny) return false;
+            if (glued_y && glued_y != cnx) return false;
+            cper_x = glued_x > 0;
+            cper_y = glued_y > 0;
+            for (int32_t k = 0; k < 2 * cnx + 2 * cny; k++) {
+                const bool periodic = k < 2 * cnx ? cper_y : cper_x;
+                if (periodic) {
+                    if (cside[k] != -2) return false;
+                    cside[k] = -1;
+                } else if (cside[k] < 0) {
+                    return false;
+                }
+            }
+            return true;
+        };
+        cart = detect();
+    }
+    if (!cart && prm->structured == 2)
+        BAD("the structured step needs a tensor-product quad mesh (cells the rectangles of two coordinate arrays, "
+            "at least two along each axis) and at most %d boundary-condition entries", kMaxTileBcs);
+
     // ---- cell order: tile-major (fused step) or reverse Cuthill-McKee
     std::vector<int32_t> perm(nc), iperm(nc);
     const bool tiled = prm->tile_cells >= 0 && D <= 4 && n_bc <= kMaxTileBcs;
@@ -440,7 +524,10 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     int32_t T = prm->tile_cells > 0 ? std::min(prm->tile_cells, B / 4) : B / 4;
     if (tiled && T < 4) BAD("tile_cells must be at least 4 (or 0 / -1)");
     std::vector<std::pair<size_t, size_t>> parts;
-    if (tiled) {
+    if (cart) {
+        for (int32_t j = 0; j < cny; j++)
+            for (int32_t i = 0; i < cnx; i++) perm[cart_index(i, j, cnx, cny)] = cart_cell[i + (size_t)cnx * j];
+    } else if (tiled) {
         for (int32_t c = 0; c < nc; c++) perm[c] = c;
         rcb(perm, 0, nc, ((int64_t)nc + T - 1) / T, cx, cy, parts);
         // rows of cells inside each tile (by centroid y, then x): the local
@@ -548,7 +635,37 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     }
     out.tile_T = 0; out.n_tiles = 0;
     out.tile_hdr.clear(); out.lgid.clear(); out.ladj.clear(); out.lfc.clear(); out.frec.clear(); out.lw.clear();
-    if (tiled) {
+    out.cart = cart;
+    if (cart) {
+        // per column / row: width, face offsets, least-squares weights of the
+        // two stencil points along that axis (the neighbour centre, its
+        // periodic image, or the wall face midpoint), inverse width
+        auto axis = [](const std::vector<double> &xs, int32_t n, bool periodic, std::vector<double> &v) {
+            v.assign((size_t)n * kCartVals, 0.0);
+            const double L = xs[n] - xs[0];
+            auto ctr = [&](int32_t i) { return 0.5 * (xs[i] + xs[i + 1]); };
+            for (int32_t i = 0; i < n; i++) {
+                const double c = ctr(i), w = xs[i + 1] - xs[i];
+                const double hl = xs[i] - c, hr = xs[i + 1] - c;
+                double dm, dp;   // distances to the left and right stencil points
+                if (i > 0) dm = c - ctr(i - 1);
+                else dm = periodic ? c - (ctr(n - 1) - L) : -hl;
+                if (i < n - 1) dp = ctr(i + 1) - c;
+                else dp = periodic ? (ctr(0) + L) - c : hr;
+                const double den = dp * dp + dm * dm;
+                double *r = &v[(size_t)i * kCartVals];
+                r[0] = w; r[1] = hl; r[2] = hr; r[3] = -dm / den; r[4] = dp / den; r[5] = 1.0 / w;
+            }
+        };
+        axis(cxs, cnx, cper_x, out.col);
+        axis(cys, cny, cper_y, out.row);
+        out.nx = cnx; out.ny = cny; out.per_x = cper_x; out.per_y = cper_y;
+        out.ntx = (cnx + kCartTX - 1) / kCartTX;
+        out.nty = (cny + kCartTY - 1) / kCartTY;
+        out.side = cside;
+        out.n_tiles = out.ntx * out.nty;
+        out.tile_T = kCartTX * kCartTY;
+    } else if (tiled) {
         if (!build_tiles(out, parts)) BAD("internal: the two views of a face are not exact mirrors");
         if (tile_lds_bytes(out.nl_max, out.na_max, out.nt_max, n_bc) > kTileLdsLimit || out.nl_max > B) {
             // one thread per local cell and LDS for all of them: bisect into smaller tiles

@@ -71,7 +71,35 @@ struct MeshBuild {
     std::vector<int16_t> lfc;
     std::vector<double> frec;
     std::vector<double> lw;
+    // Structured step (tensor-product quad meshes; cart == true): the cells
+    // are (i, j), 0 <= i < nx, 0 <= j < ny, with corners (xs[i], ys[j]) ..
+    // (xs[i+1], ys[j+1]); tiles of kCartTX x kCartTY cells in row-major tile
+    // order, cells row-major inside each tile (the internal order).  Per
+    // column i, col[i][kCartVals]: width, offsets of its left and right face
+    // midpoints from its centre, least-squares weights of its left and right
+    // stencil points (neighbour centre, periodic image, or the wall face
+    // midpoint), inverse width; per row the same in y.  Boundary-condition
+    // entry of every boundary face of the four sides (-1 where periodic):
+    // side[0..nx) bottom, [nx..2nx) top, [2nx..2nx+ny) left, then right.
+    bool cart = false;
+    int32_t nx = 0, ny = 0, ntx = 0, nty = 0, per_x = 0, per_y = 0;
+    std::vector<double> col, row;
+    std::vector<int32_t> side;
 };
+
+// Tile of the structured step and the per-column / per-row record length.
+constexpr int32_t kCartTX = 16, kCartTY = 7;
+constexpr int32_t kCartVals = 8;   // width, left offset, right offset, left weight, right weight, 1/width, pad, pad
+// Internal index of cell (i, j) of a structured mesh: tiles in row-major
+// order, each tile's cells in rows; the last tile column and row may be
+// narrower.
+__host__ __device__ inline int32_t cart_index(int32_t i, int32_t j, int32_t nx, int32_t ny)
+{
+    const int32_t tx = i / kCartTX, ty = j / kCartTY;
+    const int32_t h = ny - ty * kCartTY < kCartTY ? ny - ty * kCartTY : kCartTY;
+    const int32_t w = nx - tx * kCartTX < kCartTX ? nx - tx * kCartTX : kCartTX;
+    return ty * kCartTY * nx + tx * kCartTX * h + (j - ty * kCartTY) * w + (i - tx * kCartTX);
+}
 
 // Accelerator complex dies of an MI355X, each with its own L2: the fused step
 // gives each a contiguous range of tiles.

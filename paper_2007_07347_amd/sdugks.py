@@ -40,7 +40,8 @@ class Params(C.Structure):
     _fields_ = [("nu", C.c_double), ("tau", C.c_double), ("cfl", C.c_double), ("dt", C.c_double),
                 ("rho0", C.c_double), ("u0", C.c_double), ("v0", C.c_double), ("precision", C.c_int32),
                 ("macro_flux", C.c_int32), ("reorder", C.c_int32), ("residual_interval", C.c_int32),
-                ("tile_cells", C.c_int32), ("block_threads", C.c_int32), ("scheme", C.c_int32)]
+                ("tile_cells", C.c_int32), ("block_threads", C.c_int32), ("scheme", C.c_int32),
+                ("structured", C.c_int32)]
 
 
 _lib = C.CDLL(LIB_PATH)
@@ -48,7 +49,7 @@ _P = C.c_void_p
 _sig = {
     "sdugks_geometry": [_P, _P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P],
     "sdugks_state_bytes": [_P, _P, C.c_int32, _P, _P],
-    "sdugks_tiling": [_P, _P, C.c_int32, _P, _P, _P, _P, _P],
+    "sdugks_tiling": [_P, _P, C.c_int32, _P, _P, _P, _P, _P, _P],
     "sdugks_create": [_P, _P, C.c_int32, _P, _P, _P, C.c_size_t, _P],
     "sdugks_step": [_P, C.c_int64],
     "sdugks_step_eager": [_P, C.c_int64],
@@ -100,7 +101,7 @@ class _Inputs:
 
     def __init__(self, mesh, bcs, nu=0.0, tau=0.0, cfl=0.5, dt=0.0, rho0=1.0, u0=0.0, v0=0.0,
                  precision=FP64, macro=MACRO_CURRENT, reorder=True, residual_interval=1000, tile_cells=0,
-                 block_threads=0, scheme=0):
+                 block_threads=0, scheme=0, structured=0):
         self.xy = np.ascontiguousarray(mesh["node_xy"], dtype=np.float64)
         self.cp = np.ascontiguousarray(mesh["cell_ptr"], dtype=np.int32)
         self.cn = np.ascontiguousarray(mesh["cell_nodes"], dtype=np.int32)
@@ -114,7 +115,7 @@ class _Inputs:
             self.bcs[k] = BC(b["type"], b.get("partner", -1), b.get("rho", 1.0), b.get("u", 0.0), b.get("v", 0.0),
                              b.get("shift", (0.0, 0.0))[0], b.get("shift", (0.0, 0.0))[1])
         self.prm = Params(nu, tau, cfl, dt, rho0, u0, v0, precision, macro, 1 if reorder else 0, residual_interval,
-                          tile_cells, block_threads, scheme)
+                          tile_cells, block_threads, scheme, structured)
         self.n_cells = len(self.cp) - 1
 
     def args(self):
@@ -138,11 +139,13 @@ def geometry(mesh, bcs, **kw):
 
 def tiling(mesh, bcs, **kw):
     """Host-only: tile size, tile count and the largest local / first-ring
-    cell counts of the fused step for this mesh (tile size 0: two-kernel step)."""
+    cell counts of the fused step for this mesh (tile size 0: two-kernel
+    step), and whether the structured step is used."""
     inp = _Inputs(mesh, bcs, **kw)
-    v = [C.c_int32() for _ in range(4)]
+    v = [C.c_int32() for _ in range(5)]
     _check(_lib.sdugks_tiling(*inp.args(), *[C.byref(x) for x in v]))
-    return {"tile_cells": v[0].value, "n_tiles": v[1].value, "max_local": v[2].value, "max_ring1": v[3].value}
+    return {"tile_cells": v[0].value, "n_tiles": v[1].value, "max_local": v[2].value, "max_ring1": v[3].value,
+            "structured": bool(v[4].value)}
 
 
 def state_bytes(mesh, bcs, **kw):

@@ -144,9 +144,13 @@ def test_batch_autotuner_times_every_candidate(sd, tmp_path):
     assert [(r["tile_cells"], r["block_threads"]) for r in table] == cands
     assert all(r["ms"] is not None and r["ms"] > 0 for r in table)
     fastest = min(table, key=lambda r: r["ms"])
-    assert best == {"tile_cells": fastest["tile_cells"], "block_threads": fastest["block_threads"]}
+    assert best == {"tile_cells": fastest["tile_cells"], "block_threads": fastest["block_threads"], "structured": 1}
     again, _ = autotune.autotune_batch(problems, candidates=cands, steps=5, cache=cache)
     assert again == best
+    # without a candidate list, tensor-product meshes also try the structured step
+    best, table = autotune.autotune_batch(problems, steps=5, cache=None)
+    assert table[0]["structured"] == 2 and len(table) == 1 + len(autotune.CANDIDATES)
+    assert autotune.label(best) in {autotune.label(r) for r in table}
 
 
 @pytest.mark.parametrize("sched", [(64, 256), (32, 128)])

@@ -112,8 +112,11 @@ def _small_cases():
     }
 
 
-PATHS = {"fused": dict(tile_cells=0), "fused_t16_b64": dict(tile_cells=16, block_threads=64),
-         "two_kernel": dict(tile_cells=-1)}
+# "fused": the library's choice (the structured step on tensor-product quad
+# meshes, the general fused step otherwise); "general": the general fused step
+# on every mesh
+PATHS = {"fused": dict(tile_cells=0), "general": dict(structured=1),
+         "fused_t16_b64": dict(tile_cells=16, block_threads=64), "two_kernel": dict(tile_cells=-1)}
 
 
 @pytest.mark.parametrize("name", sorted(_small_cases()))
@@ -131,7 +134,7 @@ def test_random_state_window(sd, oracle_mod, name, macro, path):
     if macro == 0:
         kw = dict(kw, tau=0.0, cfl=0.2)
     say("window", name, "macro", macro, "path", path)
-    okw = {k: v for k, v in kw.items() if k not in ("tile_cells", "block_threads")}
+    okw = {k: v for k, v in kw.items() if k not in ("tile_cells", "block_threads", "structured")}
     o = oracle_mod.Oracle(mesh, bcs, macro=macro, **okw)
     if macro == 0 and o.dt > 2.0 * o.tau:
         pytest.skip("lagged flux is unstable at this dt/tau")

@@ -84,8 +84,8 @@ def test_tiles_are_compact(lib):
     workgroup) are 8x8 or 4x16 blocks (the stretched mesh splits unevenly), so
     at most 40 first-ring cells, and every local cell fits one thread."""
     mesh, bcs = meshgen.cavity(256)
-    t = lib.tiling(mesh, bcs, nu=1e-4)
-    assert t["tile_cells"] == 64 and t["n_tiles"] == 1024
+    t = lib.tiling(mesh, bcs, nu=1e-4, structured=1)
+    assert t["tile_cells"] == 64 and t["n_tiles"] == 1024 and not t["structured"]
     assert t["max_ring1"] <= 64 + 40 and t["max_local"] <= 256
     for tc, bt in ((16, 64), (32, 128), (200, 256)):
         t = lib.tiling(mesh, bcs, nu=1e-4, tile_cells=tc, block_threads=bt)
@@ -166,3 +166,33 @@ def test_empty_mesh_is_rejected(lib):
     empty = {"node_xy": np.zeros((0, 2)), "cell_ptr": np.zeros(1, np.int32), "cell_nodes": np.zeros(0, np.int32),
              "bedge_nodes": np.zeros((0, 2), np.int32), "bedge_tag": np.zeros(0, np.int32)}
     _expect_einval(lib, empty, [meshgen.bc(meshgen.WALL)], "empty")
+
+
+def test_structured_step_selection(lib):
+    """Tensor-product quad meshes take the structured step by default: its
+    16 x 7-cell tiles cover the grid (ragged tiles at the far edges), in any
+    cell order and with periodic sides; other meshes, an explicit tile size,
+    structured=1 and meshes whose quads are not the rectangles of two
+    coordinate arrays take the general step, and structured=2 refuses them."""
+    t = lib.tiling(*meshgen.cavity(256), nu=1e-4)
+    assert t["structured"] and t["tile_cells"] == 112 and t["n_tiles"] == 16 * 37
+    t = lib.tiling(*meshgen.cavity(23), nu=1e-4)
+    assert t["structured"] and t["n_tiles"] == 2 * 4
+    for mesh, bcs in (meshgen.couette(4, 32), meshgen.periodic_box(18, 9), meshgen.inlet_outlet_box(13, 9),
+                      (meshgen.relabel(meshgen.cavity(17)[0], seed=2)[0], meshgen.cavity(17)[1])):
+        assert lib.tiling(mesh, bcs, nu=1e-3)["structured"]
+    assert not lib.tiling(*meshgen.cavity(64), nu=1e-3, tile_cells=32)["structured"]
+    assert not lib.tiling(*meshgen.cavity(64), nu=1e-3, structured=1)["structured"]
+    assert lib.tiling(*meshgen.cavity(64), nu=1e-3, tile_cells=32, structured=2)["structured"]
+    others = [meshgen.cylinder_ogrid(40, 12, seed=1), meshgen.jittered_periodic_triangles(9, seed=1),
+              meshgen.rotate(*meshgen.couette(5, 12), 0.37),
+              (meshgen.split_some(meshgen.cavity(17)[0], 0.3, seed=4), meshgen.cavity(17)[1])]
+    for mesh, bcs in others:
+        assert not lib.tiling(mesh, bcs, nu=1e-3)["structured"]
+        with pytest.raises(lib.SdugksError) as ei:
+            lib.tiling(mesh, bcs, nu=1e-3, structured=2)
+        assert ei.value.code == lib.EINVAL
+    # a one-cell-wide grid has no two-sided stencil along that axis
+    assert not lib.tiling(*meshgen.couette(1, 8), nu=1e-2)["structured"]
+    with pytest.raises(lib.SdugksError):
+        lib.tiling(*meshgen.cavity(8), nu=1e-3, structured=3)
