@@ -269,6 +269,24 @@ int sdugks_batch_step(sdugks_batch_t *b, int64_t n);
 int sdugks_batch_residual(sdugks_batch_t *b, double *eps);
 int sdugks_batch_destroy(sdugks_batch_t *b);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * residuals of sdugks_batch_residual for up to 1024 handles without a batch
+ * object and without any allocation -- no hipMalloc, hipFree, events or
+ * streams are created; the per-member results go through one file-scope
+ * device array of 32 KiB (1024 x 4 doubles), held by each device the library
+ * runs on until the process ends, and the job table travels in the kernel
+ * arguments.  Same values, bitwise, as sdugks_residual and
+ * sdugks_batch_residual (each member re-snapshotted).
+ *   members: n distinct handles, 1 <= n <= 1024 (SDUGKS_EINVAL beyond), all
+ *            on one device and created with the same stream, on which the
+ *            work is enqueued (the call then synchronises that stream);
+ *   eps:     host [n], filled as sdugks_batch_residual does (NaN and
+ *            SDUGKS_EDIVERGED for a non-finite member).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (from two threads, or on two streams) race and must not be made. */
+int sdugks_residuals_static(sdugks_t *const *members, int32_t n, double *eps);
+
 /* Failure injection for tests: writes NaN into f of one cell and velocity
  * (caller cell order). */
 int sdugks_debug_poison(sdugks_t *h, int32_t cell, int32_t i);

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsdugks.so")
-SOURCES = ["api.cpp", "mesh.cpp", "kernels.hip", "step_tiled.hip", "boundary.hip", "step_cart.hip"]
+SOURCES = ["api.cpp", "mesh.cpp", "kernels.hip", "step_tiled.hip", "boundary.hip", "noalloc.hip", "step_cart.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              # packed FP32 instructions are kept out of every kernel
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

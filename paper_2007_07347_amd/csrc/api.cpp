@@ -1258,6 +1258,54 @@ int sdugks_batch_residual(sdugks_batch_t *b, double *eps)
                : SDUGKS_OK;
 }
 
+int sdugks_residuals_static(sdugks_t *const *members, int32_t n, double *eps)
+{
+    if (!members || !eps || n <= 0) return fail(SDUGKS_EINVAL, "bad arguments");
+    if (n > kNoAllocMaxMembers)
+        return fail(SDUGKS_EINVAL, "sdugks_residuals_static takes at most " + std::to_string(kNoAllocMaxMembers) +
+                                       " members");
+    for (int32_t k = 0; k < n; k++) {
+        if (!members[k]) return fail(SDUGKS_EINVAL, "null member");
+        if (members[k]->stream != members[0]->stream || members[k]->device != members[0]->device)
+            return fail(SDUGKS_EINVAL, "sdugks_residuals_static: all members must share one device and one stream");
+        for (int32_t j = 0; j < k; j++)
+            if (members[j] == members[k]) return fail(SDUGKS_EINVAL, "a handle appears twice");
+    }
+    const int dev = members[0]->device;
+    hipStream_t st = members[0]->stream;
+    HIPCHK(hipSetDevice(dev));
+    double *out = nullptr;
+    HIPCHK(noalloc_scratch(dev, &out));
+    // the job table on the stack: it is copied into the kernel arguments
+    ReduceJob jobs[kNoAllocPack];
+    for (int32_t k0 = 0; k0 < n; k0 += kNoAllocPack) {
+        const int m = std::min<int32_t>(kNoAllocPack, n - k0);
+        for (int k = 0; k < m; k++) {
+            const sdugks_t *h = members[k0 + k];
+            jobs[k] = ReduceJob{h->mb.nc, (int32_t)h->L.np, h->at<double>(h->L.off_W[h->cur]),
+                                h->at<double>(h->L.off_area), h->at<double>(h->L.off_snap),
+                                h->at<double>(h->L.off_part)};
+        }
+        HIPCHK(launch_reduce_packs(jobs, m, out + 4 * (size_t)k0, st));
+    }
+    double res[4 * kNoAllocMaxMembers];
+    HIPCHK(hipMemcpyAsync(res, out, (size_t)n * 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool bad = false;
+    for (int32_t k = 0; k < n; k++) {
+        const double *r = res + 4 * k;
+        if (r[3] != 0.0) {
+            members[k]->diverged = true;
+            eps[k] = NAN;
+            bad = true;
+        } else {
+            eps[k] = r[1] > 0 ? std::sqrt(r[0]) / std::sqrt(r[1]) : INFINITY;
+        }
+    }
+    return bad ? fail(SDUGKS_EDIVERGED, "non-finite density or velocity in a member (its residual is NaN)")
+               : SDUGKS_OK;
+}
+
 int sdugks_debug_batch_fail(sdugks_batch_t *b)
 {
     if (!b) return fail(SDUGKS_EINVAL, "null batch");

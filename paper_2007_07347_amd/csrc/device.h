@@ -192,6 +192,20 @@ struct ReduceJob {
 };
 // Residuals of n members at once: out [n][4] as launch_reduce's out4 each.
 hipError_t launch_reduce_batch(const ReduceJob *jobs, int n, double *out, hipStream_t st);
+// Residuals of n members without any allocation: the per-member results
+// [n][4] go to the file-scope scratch array of noalloc.hip (at most
+// kNoAllocMaxMembers members), the job table travels in the kernel arguments
+// (kNoAllocPack members per launch).
+constexpr int kNoAllocMaxMembers = 1024;
+constexpr int kNoAllocPack = 32;
+constexpr int kNoAllocMaxDevices = 64;
+struct ReducePack {
+    ReduceJob jobs[kNoAllocPack];
+};
+// The device address of this device's scratch array ([kNoAllocMaxMembers][4]
+// doubles), looked up once per device.
+hipError_t noalloc_scratch(int device, double **out);
+hipError_t launch_reduce_packs(const ReduceJob *jobs, int n, double *out, hipStream_t st);
 // f = feq of the macros m3 = [3][np] (rho, u, v) (FP64 f, or with f32 the
 // FP32 deviation from w_i rho0, or zero -- the non-equilibrium part -- when
 // rho0 < 0), W, G = 0 and the residual snapshot.

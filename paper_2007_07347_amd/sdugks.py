@@ -68,6 +68,7 @@ _sig = {
     "sdugks_batch_set_members": [_P, _P, C.c_int32],
     "sdugks_batch_step": [_P, C.c_int64],
     "sdugks_batch_residual": [_P, _P],
+    "sdugks_residuals_static": [_P, C.c_int32, _P],
     "sdugks_debug_batch_fail": [_P],
     "sdugks_batch_destroy": [_P],
     "sdugks_debug_poison": [_P, C.c_int32, C.c_int32],
