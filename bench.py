@@ -49,7 +49,15 @@ RESIDUAL_INTERVAL = 1000
 ALG_BYTES = {"f64": 2 * (72 + 24) + 184, "fp32dev": 2 * (36 + 24) + 184}
 # triangles: three faces per cell, 144 B of geometry per cell instead of 184
 ALG_BYTES_TRI = {"f64": 2 * (72 + 24) + 144, "fp32dev": 2 * (36 + 24) + 144}
-KERNEL_SRC = os.path.join(ROOT, "paper_2007_07347_amd", "csrc", "step_tiled.hip")
+_CSRC = os.path.join(ROOT, "paper_2007_07347_amd", "csrc")
+# the sources each step kernel is compiled from (its own file and the shared
+# device helpers): the traffic counters of a kernel hold while these are unchanged
+KERNEL_SOURCES = {
+    "k_step_tiled": ("step_tiled.hip", "step_common.h"),
+    "k_step_batch": ("step_tiled.hip", "step_common.h"),
+    "k_step_cart": ("step_cart.hip", "step_common.h"),
+    "k_step_batch_cart": ("step_cart.hip", "step_common.h"),
+}
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 SECTIONS = ("cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large")
 
@@ -92,9 +100,14 @@ def code_hash(text):
     return hashlib.sha1("\n".join(ln for ln in lines if ln).encode()).hexdigest()[:16]
 
 
-def kernel_hash():
-    with open(KERNEL_SRC) as fh:
-        return code_hash(fh.read())
+def kernel_hash(kernel="k_step_tiled"):
+    """code_hash of the sources of a step kernel, named with or without its
+    template arguments ("k_step_batch_cart<1>" or "k_step_batch_cart")."""
+    text = []
+    for f in KERNEL_SOURCES[kernel.split("<")[0]]:
+        with open(os.path.join(_CSRC, f)) as fh:
+            text.append(fh.read())
+    return code_hash("\n".join(text))
 
 
 def measured_traffic(workload, schedule=None):
@@ -106,7 +119,7 @@ def measured_traffic(workload, schedule=None):
     except (OSError, ValueError):
         return None
     e = t.get(workload)
-    if not e or e.get("kernel_code_sha1") != kernel_hash():
+    if not e or e.get("kernel_code_sha1") != kernel_hash(e.get("kernel", "k_step_tiled")):
         return None
     if schedule is not None and e.get("schedule") not in (None, schedule):
         return None
@@ -561,7 +574,7 @@ def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50, schedule
         kw = dict(nu=0.1 / 40, cfl=0.5, u0=0.1, precision=prec)
         if schedule:
             t, b = (int(x) for x in schedule.split(","))
-            sched = {"tile_cells": t, "block_threads": b}
+            sched = {"tile_cells": t, "block_threads": b, "structured": 1}
         else:
             sched, _ = autotune.autotune(mesh, bcs, steps=100, **kw)
         s = sdugks.Solver(mesh, bcs, **sched, **kw)
@@ -575,7 +588,8 @@ def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50, schedule
         alg = ALG_BYTES_TRI[pname] * nc / (ms / 1e3) / 1e9
         out[pname] = {"mlups": round(nc / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5), "schedule": sched,
                       "alg_bytes_per_cell": ALG_BYTES_TRI[pname], "achieved_GBs": round(alg, 1),
-                      "frac_of_hbm_peak": round(alg / HBM_PEAK_GBS, 4)}
+                      "frac_of_hbm_peak": round(alg / HBM_PEAK_GBS, 4),
+                      "traffic_bytes_per_launch": measured_traffic(f"cylinder200k_{pname}", sched)}
     d = uv["fp32dev"] - uv["f64"]
     out["fp32dev_velocity_rel_l2_vs_f64"] = float(np.linalg.norm(d) / np.linalg.norm(uv["f64"]))
     progress(f"cylinder 200k: fp32dev {out['fp32dev']['mlups']} / f64 {out['f64']['mlups']} MLUPS")
@@ -585,15 +599,22 @@ def cylinder200k_form(sdugks, autotune, meshgen, steps=2000, warmup=50, schedule
 def large_form(sdugks, meshgen, n=2048, steps=100, warmup=20):
     """Lid-driven cavity on n x n tanh quads (n = 2048: 4.2M cells, device
     state above 2 GB, far beyond the 256 MB Infinity Cache), Re 1000, FP64 and
-    FP32 deviation, 64-cell tiles: MLUPS and the step's share of the HBM peak,
-    from the algorithmic bytes and, while the committed counters match the
-    kernel, from the measured HBM traffic."""
+    FP32 deviation, on the general step's 64-cell tiles and on the structured
+    step: MLUPS and the step's share of the HBM peak, from the algorithmic
+    bytes and, while the committed counters match the kernel, from the
+    measured HBM traffic.  The structured step reads no geometry tables, so
+    its own compulsory bytes (the state, read and written once) are given too."""
     import torch
     mesh, bcs = meshgen.cavity(n, beta=1.5, U=0.1)
-    out = {"workload": f"lid-driven cavity {n}x{n} tanh(1.5) quads, Re 1000, CFL 0.5, tiles of 64 cells, "
-                       f"{steps} steps after {warmup}"}
-    for prec, pname in ((sdugks.FP64, "f64"), (sdugks.FP32DEV, "fp32dev")):
-        kw = dict(nu=1e-4, cfl=0.5, precision=prec, tile_cells=64, block_threads=256)
+    out = {"workload": f"lid-driven cavity {n}x{n} tanh(1.5) quads, Re 1000, CFL 0.5, general step on tiles of "
+                       f"64 cells and structured step, {steps} steps after {warmup}"}
+    general = {"tile_cells": 64, "block_threads": 256, "structured": 1}
+    forms = [(sdugks.FP64, "f64", general), (sdugks.FP32DEV, "fp32dev", general),
+             (sdugks.FP64, "structured_f64", {"structured": 2}),
+             (sdugks.FP32DEV, "structured_fp32dev", {"structured": 2})]
+    for prec, name, sched in forms:
+        pname = "f64" if prec == sdugks.FP64 else "fp32dev"
+        kw = dict(nu=1e-4, cfl=0.5, precision=prec, **sched)
         s = sdugks.Solver(mesh, bcs, **kw)
         s.step(warmup)
         torch.cuda.synchronize()
@@ -601,16 +622,20 @@ def large_form(sdugks, meshgen, n=2048, steps=100, warmup=20):
         nc = s.n_cells
         s.close()
         alg = ALG_BYTES[pname] * nc / (ms / 1e3) / 1e9
-        e = {"mlups": round(nc / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5),
+        e = {"mlups": round(nc / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms, 5), "schedule": sched,
              "working_set_GB": round(sdugks.state_bytes(mesh, bcs, **kw) / 1e9, 2),
              "achieved_GBs": round(alg, 1), "frac_of_hbm_peak": round(alg / HBM_PEAK_GBS, 4)}
-        t = measured_traffic(f"cavity{n}_{pname}", {"tile_cells": 64, "block_threads": 256})
+        if sched.get("structured") == 2:
+            own = 2 * ((72 if prec == sdugks.FP64 else 36) + 24)
+            e["kernel_own_bytes_per_cell"] = own
+            e["frac_of_own_bytes"] = round(own * nc / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+        t = measured_traffic(f"cavity{n}_{name}", sched)
         if t is not None:
             e["traffic_bytes_per_launch"] = t
             e["measured_GBs"] = round(t / (ms / 1e3) / 1e9, 1)
             e["measured_frac_of_hbm_peak"] = round(t / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-        out[pname] = e
-        progress(f"large cavity {pname}: {e['mlups']} MLUPS, {e['frac_of_hbm_peak']} of HBM peak (algorithmic)")
+        out[name] = e
+        progress(f"large cavity {name}: {e['mlups']} MLUPS, {e['frac_of_hbm_peak']} of HBM peak (algorithmic)")
     return out
 
 
@@ -740,7 +765,7 @@ def main():
     roof = {"bound": "hbm", "kernel": "k_step_batch_cart" if structured else "k_step_batch",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("batch64_fp32dev", hb["sched"]),
+            "traffic": measured_traffic("batch64_fp32dev" + ("" if structured else "_general"), hb["sched"]),
             "alg_bytes_per_cell": ALG_BYTES["fp32dev"], "cells_per_launch": cells, "kernel_ms": round(k_ms, 5),
             "working_set_MB": hb["working_set_MB"],
             "note": "working set above the 256 MB Infinity Cache; achieved = algorithmic bytes per cell (the "

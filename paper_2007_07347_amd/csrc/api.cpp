@@ -351,8 +351,9 @@ int sdugks_tiling(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     if (rc) return rc;
     if (tile_cells) *tile_cells = mb.tile_T;
     if (n_tiles) *n_tiles = mb.n_tiles;
-    if (max_local) *max_local = mb.cart ? (kCartTX + 4) * (kCartTY + 4) : mb.nl_max;
-    if (max_ring1) *max_ring1 = mb.cart ? (kCartTX + 2) * (kCartTY + 2) : mb.na_max;
+    const int32_t rows = cart_tile_rows(prm->precision);
+    if (max_local) *max_local = mb.cart ? (kCartTX + 4) * (rows + 4) : mb.nl_max;
+    if (max_ring1) *max_ring1 = mb.cart ? (kCartTX + 2) * (rows + 2) : mb.na_max;
     if (structured) *structured = mb.cart ? 1 : 0;
     return SDUGKS_OK;
 }
@@ -965,7 +966,7 @@ int batch_build_tables(sdugks_batch_t *b)
         for (auto &x : want) if (x.D == D && x.mode == mode && x.cart == cart) g = &x;
         if (!g) { want.emplace_back(); g = &want.back(); g->D = D; g->mode = mode; g->cart = cart; }
         g->members.push_back((int)k);
-        g->block = cart ? 256 : std::max(g->block, h->block);
+        g->block = cart ? step_cart_threads(mode) : std::max(g->block, h->block);
         g->lds = std::max(g->lds, cart ? step_cart_lds_bytes(mode, (int)h->mb.bcs.size())
                                        : step_tiled_lds_bytes(h->dt, mode, (int)h->mb.bcs.size()));
         g->n_inst++;
@@ -981,8 +982,12 @@ int batch_build_tables(sdugks_batch_t *b)
         batch_release_graph(b);
         batch_release_groups(b);
         for (auto &g : want) {
+            // tile slots: the live tiles rounded up to a sixteenth of their
+            // power of two (at most 1/8 of the grid empty, room for members
+            // that join later without a rebuild)
+            const int32_t q = std::max<int32_t>(kXcds, (int32_t)(next_pow2(g.n_tiles) / 16));
             g.cap_inst = (int)next_pow2(g.n_inst);
-            g.cap_tiles = (int)next_pow2(g.n_tiles);
+            g.cap_tiles = std::max(q, (g.n_tiles + q - 1) / q * q);
             // LDS exactly the largest member's: a spare margin for later members
             // would cost resident workgroups per CU on every step (a member that
             // needs more rebuilds the group, like one that exceeds a capacity)

@@ -162,12 +162,14 @@ hipError_t launch_flux_update(const DevMesh &m, const DevState &s, const DevScra
 hipError_t launch_step_tiled(const DevMesh &m, const DevTiles &t, const DevState &s, int lagged, int mode,
                              int block, hipStream_t st, GraphChain *gc = nullptr);
 size_t step_tiled_lds_bytes(const DevTiles &t, int mode, int n_bc);
-// Structured step over 16 x 7-cell tiles of a tensor-product quad mesh (one
-// workgroup of 256 threads per tile), and its batched form (members of one
-// mode on the structured step).
+// Structured step over the tiles of a tensor-product quad mesh (one
+// workgroup per tile: 16 x 14 cells on 512 threads for FP32 deviations, 16 x 7
+// on 256 threads otherwise), and its batched form (members of one mode on the
+// structured step).
 hipError_t launch_step_cart(const DevMesh &m, const DevCart &c, const DevState &s, int lagged, int mode,
                             hipStream_t st, GraphChain *gc = nullptr);
 size_t step_cart_lds_bytes(int mode, int n_bc);
+int step_cart_threads(int mode);
 hipError_t launch_step_batch_cart(const BatchTable &tab, int mode, int parity, int cap_tiles, size_t lds,
                                   hipStream_t st, GraphChain *gc = nullptr);
 // Batched fused step over the tiles of all members (same D class and mode).

@@ -455,6 +455,8 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
             cnx = (int32_t)cxs.size() - 1;
             cny = (int32_t)cys.size() - 1;
             if (cnx < 2 || cny < 2 || (int64_t)cnx * cny != nc) return false;
+            // the step addresses each velocity's row of f with 32-bit byte offsets
+            if ((int64_t)nc > (1LL << 29) - 4096) return false;
             cart_cell.assign((size_t)nc, -1);
             std::vector<int32_t> ci(nc), cj(nc);
             for (int32_t c = 0; c < nc; c++) {
@@ -660,11 +662,12 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
         axis(cxs, cnx, cper_x, out.col);
         axis(cys, cny, cper_y, out.row);
         out.nx = cnx; out.ny = cny; out.per_x = cper_x; out.per_y = cper_y;
+        const int32_t rows = cart_tile_rows(prm->precision);
         out.ntx = (cnx + kCartTX - 1) / kCartTX;
-        out.nty = (cny + kCartTY - 1) / kCartTY;
+        out.nty = (cny + rows - 1) / rows;
         out.side = cside;
         out.n_tiles = out.ntx * out.nty;
-        out.tile_T = kCartTX * kCartTY;
+        out.tile_T = kCartTX * rows;
     } else if (tiled) {
         if (!build_tiles(out, parts)) BAD("internal: the two views of a face are not exact mirrors");
         if (tile_lds_bytes(out.nl_max, out.na_max, out.nt_max, n_bc) > kTileLdsLimit || out.nl_max > B) {

@@ -73,8 +73,9 @@ struct MeshBuild {
     std::vector<double> lw;
     // Structured step (tensor-product quad meshes; cart == true): the cells
     // are (i, j), 0 <= i < nx, 0 <= j < ny, with corners (xs[i], ys[j]) ..
-    // (xs[i+1], ys[j+1]); tiles of kCartTX x kCartTY cells in row-major tile
-    // order, cells row-major inside each tile (the internal order).  Per
+    // (xs[i+1], ys[j+1]); storage tiles of kCartTX x kCartTY cells in
+    // row-major tile order, cells row-major inside each tile (the internal
+    // order); ntx x nty step tiles of kCartTX x cart_tile_rows(precision).  Per
     // column i, col[i][kCartVals]: width, offsets of its left and right face
     // midpoints from its centre, least-squares weights of its left and right
     // stencil points (neighbour centre, periodic image, or the wall face
@@ -87,8 +88,16 @@ struct MeshBuild {
     std::vector<int32_t> side;
 };
 
-// Tile of the structured step and the per-column / per-row record length.
-constexpr int32_t kCartTX = 16, kCartTY = 7;
+// Storage tile of the structured step (16 x 14 cells) and the per-column /
+// per-row record length.  The FP32-deviation step works on whole storage
+// tiles; the forms with FP64 face arithmetic on their upper and lower halves
+// (16 x 7), whose cells are contiguous too, so that their LDS (twice the
+// bytes per value) stays small enough for several workgroups per CU.
+constexpr int32_t kCartTX = 16, kCartTY = 14;
+__host__ __device__ constexpr int32_t cart_tile_rows(int precision)
+{
+    return precision == SDUGKS_FP32DEV ? kCartTY : kCartTY / 2;
+}
 constexpr int32_t kCartVals = 8;   // width, left offset, right offset, left weight, right weight, 1/width, pad, pad
 // Internal index of cell (i, j) of a structured mesh: tiles in row-major
 // order, each tile's cells in rows; the last tile column and row may be

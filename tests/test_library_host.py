@@ -170,14 +170,21 @@ def test_empty_mesh_is_rejected(lib):
 
 def test_structured_step_selection(lib):
     """Tensor-product quad meshes take the structured step by default: its
-    16 x 7-cell tiles cover the grid (ragged tiles at the far edges), in any
-    cell order and with periodic sides; other meshes, an explicit tile size,
-    structured=1 and meshes whose quads are not the rectangles of two
-    coordinate arrays take the general step, and structured=2 refuses them."""
+    tiles (16 x 7 cells; 16 x 14 for FP32 deviations) cover the grid (ragged
+    tiles at the far edges), in any cell order and with periodic sides; other
+    meshes, an explicit tile size, structured=1 and meshes whose quads are not
+    the rectangles of two coordinate arrays take the general step, and
+    structured=2 refuses them."""
     t = lib.tiling(*meshgen.cavity(256), nu=1e-4)
     assert t["structured"] and t["tile_cells"] == 112 and t["n_tiles"] == 16 * 37
+    assert (t["max_local"], t["max_ring1"]) == (20 * 11, 18 * 9)
+    t = lib.tiling(*meshgen.cavity(256), nu=1e-4, precision=lib.FP32DEV)
+    assert t["structured"] and t["tile_cells"] == 224 and t["n_tiles"] == 16 * 19
+    assert (t["max_local"], t["max_ring1"]) == (20 * 18, 18 * 16)
+    assert lib.tiling(*meshgen.cavity(256), nu=1e-4, precision=lib.FP32NEQ)["n_tiles"] == 16 * 37
     t = lib.tiling(*meshgen.cavity(23), nu=1e-4)
     assert t["structured"] and t["n_tiles"] == 2 * 4
+    assert lib.tiling(*meshgen.cavity(23), nu=1e-4, precision=lib.FP32DEV)["n_tiles"] == 2 * 2
     for mesh, bcs in (meshgen.couette(4, 32), meshgen.periodic_box(18, 9), meshgen.inlet_outlet_box(13, 9),
                       (meshgen.relabel(meshgen.cavity(17)[0], seed=2)[0], meshgen.cavity(17)[1])):
         assert lib.tiling(mesh, bcs, nu=1e-3)["structured"]
