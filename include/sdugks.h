@@ -121,9 +121,11 @@ typedef struct {
     int32_t scheme;               /* SDUGKS_SCHEME_SIMPLIFIED (default) or SDUGKS_SCHEME_ORIGINAL */
     int32_t structured;           /* structured step for tensor-product quad meshes (the cells are the
                                      rectangles of two coordinate arrays; periodic sides glued row to row
-                                     or column to column): 0 = used when the mesh is one and tile_cells
-                                     is 0, 1 = never, 2 = required (SDUGKS_EINVAL otherwise).  It fixes
-                                     its own tiles (16 x 7 cells, 256 threads) and ignores block_threads */
+                                     or column to column; at most 2^29 - 4096 cells): 0 = used when the
+                                     mesh is one and tile_cells is 0, 1 = never, 2 = required
+                                     (SDUGKS_EINVAL otherwise).  It fixes
+                                     its own tiles (16 x 14 cells on 512 threads for FP32DEV, 16 x 7 cells on
+                                     256 threads otherwise) and ignores block_threads */
 } sdugks_params;
 
 typedef struct sdugks_s sdugks_t;
@@ -141,7 +143,8 @@ int sdugks_geometry(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, 
  * size used (0 when the two-kernel step is used: polygons with more than four
  * faces, or tile_cells = -1); n_tiles; max_local: largest tile plus both halo
  * rings; max_ring1: largest tile plus its first ring; structured: 1 when the
- * structured step is used (its tiles are 16 x 7 cells).  Outputs may be NULL. */
+ * structured step is used (its tiles are 16 x 14 cells for FP32DEV, 16 x 7 otherwise).  Outputs
+ * may be NULL. */
 int sdugks_tiling(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, const sdugks_params *prm,
                   int32_t *tile_cells, int32_t *n_tiles, int32_t *max_local, int32_t *max_ring1,
                   int32_t *structured);

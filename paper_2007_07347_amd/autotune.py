@@ -1,5 +1,5 @@
 """Autotuner of the fused step's schedule: on tensor-product quad meshes the
-structured step (fixed 16 x 7-cell tiles, one lane per face) against the
+structured step (fixed tiles, one lane per face) against the
 general fused step; for the general step, the tile size (cells per
 workgroup, which sets the halo overhead and the LDS per workgroup, hence how
 many workgroups share a compute unit) and threads per workgroup (which sets

@@ -517,7 +517,8 @@ int build_mesh(const sdugks_mesh *m, const sdugks_bc *bc, int32_t n_bc, const sd
     }
     if (!cart && prm->structured == 2)
         BAD("the structured step needs a tensor-product quad mesh (cells the rectangles of two coordinate arrays, "
-            "at least two along each axis) and at most %d boundary-condition entries", kMaxTileBcs);
+            "at least two along each axis, at most 2^29 - 4096 cells) and at most %d boundary-condition entries",
+            kMaxTileBcs);
 
     // ---- cell order: tile-major (fused step) or reverse Cuthill-McKee
     std::vector<int32_t> perm(nc), iperm(nc);
