@@ -299,7 +299,8 @@ int capture_step_graph(sdugks_t *h, int c, int64_t pairs, hipGraph_t &graph, hip
 {
     hipGraph_t gr = nullptr;
     HIPCHK(hipGraphCreate(&gr, 0));
-    GraphChain gc{gr, nullptr};
+    GraphChain gc;
+    gc.graph = gr;
     int rc = 0;
     for (int64_t k = 0; k < pairs && !rc; k++) {
         rc = launch_step_at(h, c, h->stream, &gc);
@@ -1064,13 +1065,18 @@ int batch_build(sdugks_batch_t *b)
     return rc;
 }
 
+// One batched step: a launch per group.  In a graph the groups' nodes of one
+// step depend only on the previous step's nodes (their members are disjoint),
+// so the runtime may run them side by side.
 int batch_launch(sdugks_batch_t *b, int parity, GraphChain *gc = nullptr)
 {
+    if (gc) gc->begin_fan();
     for (auto &g : b->groups) {
         BatchTable tab{g.d_inst, g.d_tmap};
         if (g.cart) HIPCHK(launch_step_batch_cart(tab, g.mode, parity, g.cap_tiles, g.lds, b->stream, gc));
         else HIPCHK(launch_step_batch(tab, g.D, g.mode, parity, g.cap_tiles, g.lds, g.block, b->stream, gc));
     }
+    if (gc) gc->end_fan();
     return SDUGKS_OK;
 }
 
@@ -1152,7 +1158,8 @@ int batch_capture(sdugks_batch_t *b, int64_t pairs, hipGraph_t &graph, hipGraphE
 {
     hipGraph_t gr = nullptr;
     HIPCHK(hipGraphCreate(&gr, 0));
-    GraphChain gc{gr, nullptr};
+    GraphChain gc;
+    gc.graph = gr;
     int rc = 0;
     for (int64_t k = 0; k < pairs && !rc; k++) {
         rc = batch_launch(b, 0, &gc);

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <tuple>
+#include <vector>
 #include <utility>
 
 namespace sdg {
@@ -118,9 +119,22 @@ struct DevScratch {
 // previous one).  Graphs are built node by node rather than by stream
 // capture, so that another thread's allocations or synchronous copies can
 // never invalidate them.
+// Kernel nodes appended to a graph.  A node depends on `deps` (the previous
+// node, or every node of the previous fan); between begin_fan and end_fan the
+// nodes are collected instead, all depending on the same `deps`, so they may
+// run concurrently, and end_fan makes the next node wait for all of them.
 struct GraphChain {
     hipGraph_t graph = nullptr;
-    hipGraphNode_t last = nullptr;
+    std::vector<hipGraphNode_t> deps;
+    std::vector<hipGraphNode_t> fan;
+    bool fanning = false;
+    void begin_fan() { fan.clear(); fanning = true; }
+    void end_fan()
+    {
+        fanning = false;
+        if (!fan.empty()) deps.swap(fan);
+        fan.clear();
+    }
 };
 
 template <typename Tup, size_t... I>
@@ -146,8 +160,11 @@ inline hipError_t emit(void (*fn)(P...), dim3 grid, dim3 blk, size_t lds, hipStr
     kp.kernelParams = ptrs;
     kp.extra = nullptr;
     hipGraphNode_t node = nullptr;
-    const hipError_t e = hipGraphAddKernelNode(&node, gc->graph, gc->last ? &gc->last : nullptr, gc->last ? 1 : 0, &kp);
-    if (e == hipSuccess) gc->last = node;
+    const hipError_t e = hipGraphAddKernelNode(&node, gc->graph, gc->deps.empty() ? nullptr : gc->deps.data(),
+                                               gc->deps.size(), &kp);
+    if (e != hipSuccess) return e;
+    if (gc->fanning) gc->fan.push_back(node);
+    else gc->deps.assign(1, node);
     return e;
 }
 
