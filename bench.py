@@ -59,7 +59,9 @@ KERNEL_SOURCES = {
     "k_step_batch_cart": ("step_cart.hip", "step_common.h"),
 }
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-SECTIONS = ("cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large")
+SECTIONS = ("cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large", "serving_full")
+# the full-range serving trace takes minutes; it runs only when named
+DEFAULT_SECTIONS = SECTIONS[:-1]
 
 
 def parse():
@@ -69,7 +71,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=40)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-extra", action="store_true", help="headline workload only")
-    p.add_argument("--sections", default=",".join(SECTIONS),
+    p.add_argument("--sections", default=",".join(DEFAULT_SECTIONS),
                    help="extra sections to run after the headline, comma-separated from " + ",".join(SECTIONS))
     p.add_argument("--schedule", default="", metavar="T,B|structured",
                    help="schedule of the 256 x 256 cavity forms instead of the autotuner's pick: the general step's "
@@ -290,9 +292,11 @@ def batch_headline(sdugks, autotune, meshgen, a, seed=2026, n_inst=64):
 
 SERVING_TRACE = dict(n_requests=24, rate=20.0, couette_n=(8, 128), cavity_n=(64, 256),
                      cylinder_cells=(10_000, 100_000), re_range=(10.0, 2000.0), cylinder_re=(10.0, 2000.0))
+# the serving workload's full ranges: cavities 64^2 to 1024^2, cylinders 10k to 1M triangles
+SERVING_TRACE_FULL = dict(SERVING_TRACE, cavity_n=(64, 1024), cylinder_cells=(10_000, 1_000_000))
 
 
-def serving(meshgen, seed=7, step_cap=300_000):
+def serving(meshgen, seed=7, step_cap=300_000, trace_kw=None):
     """Continuous-batching serving loop on a finite seeded trace (Poisson
     arrivals at 20 per second; Couette 4 x N, N in [8, 128]; cavities N x N,
     N in [64, 256]; cylinder O-grids of 10k to 100k triangles; Re in
@@ -306,7 +310,8 @@ def serving(meshgen, seed=7, step_cap=300_000):
     at its own check)."""
     import numpy as np
     from paper_2007_07347_amd import sdugks, serve
-    trace = meshgen.serving_trace(seed=seed, **SERVING_TRACE)
+    tk = SERVING_TRACE if trace_kw is None else trace_kw
+    trace = meshgen.serving_trace(seed=seed, **tk)
     rq = [serve.Request(r["rid"], r["arrival"], r["mesh"], r["bcs"], r["params"], r["kind"], r["n_cells"])
           for r in trace]
     budget = 8 << 30
@@ -330,9 +335,11 @@ def serving(meshgen, seed=7, step_cap=300_000):
         acc.append(row)
     both = [r["velocity_rel_l2"] for r in acc if r["batched"] == r["fp64_loop"] == "converged"
             and "velocity_rel_l2" in r]
-    return {"workload": f"{len(rq)} requests (Couette 4xN N in [8,128], cavity NxN N in [64,256], cylinder O-grid "
-                        f"10k-100k cells; Re 10-2000, Couette <= 40), Poisson 20/s, seed {seed}, residual 1e-7, "
-                        f"cap {step_cap} steps, HBM budget 8 GiB",
+    cn, cc = tk["cavity_n"], tk["cylinder_cells"]
+    return {"workload": f"{len(rq)} requests (Couette 4xN N in [8,128], cavity NxN N in [{cn[0]},{cn[1]}], cylinder "
+                        f"O-grid {cc[0] // 1000}k-{cc[1] // 1000}k cells; Re 10-2000, Couette <= 40), Poisson 20/s, "
+                        f"seed {seed}, residual 1e-7, cap {step_cap} steps, HBM budget 8 GiB",
+            "cells": [t["n_cells"] for t in trace],
             "batched_fp32dev": {k: (r3(v) if isinstance(v, float) else v) for k, v in st_b.items()},
             "per_case_fp64_loop": {k: (r3(v) if isinstance(v, float) else v) for k, v in st_s.items()},
             "accuracy_vs_fp64_loop": {"max_velocity_rel_l2_converged_in_both": max(both) if both else None,
@@ -798,6 +805,9 @@ def main():
     if "serving" in sections:
         out["serving"] = serving(meshgen)
         progress("serving trace done")
+    if "serving_full" in sections:
+        out["serving_full"] = serving(meshgen, step_cap=100_000, trace_kw=SERVING_TRACE_FULL)
+        progress("full-range serving trace done")
     if "cylinder" in sections:
         out["cylinder"] = cylinder_form(meshgen)
     if "original" in sections:

@@ -48,8 +48,11 @@ def test_unknown_section_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--sections", "cavity256,nope"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
-    assert set(_bench().SECTIONS) == {"cavity256", "converge", "serving", "cylinder", "cylinder200k", "original",
-                                      "large"}
+    b = _bench()
+    assert set(b.SECTIONS) == {"cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large",
+                               "serving_full"}
+    # the full-range serving trace runs only when named
+    assert "serving_full" not in b.DEFAULT_SECTIONS
 
 
 def test_cpu_model_is_named():
