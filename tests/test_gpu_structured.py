@@ -53,8 +53,12 @@ def _periodic_y_channel():
 CASES = {
     "cavity_23": (lambda: meshgen.cavity(23), dict(nu=1e-3, cfl=0.5)),
     "cavity_40x40_lid": (lambda: meshgen.cavity(40, U=0.05), dict(nu=4e-4, cfl=0.5)),
+    # a last tile column one cell wide, ragged tile rows of both shapes
+    "cavity_33": (lambda: meshgen.cavity(33), dict(nu=1e-3, cfl=0.5)),
     "couette_4x32": (lambda: meshgen.couette(4, 32, 0.1), dict(nu=0.01, cfl=0.5)),
     "periodic_box_18x9": (lambda: meshgen.periodic_box(18, 9), dict(nu=0.004, cfl=0.5)),
+    # several full tiles of either shape in both directions, wrapped across tiles
+    "periodic_box_40x30": (lambda: meshgen.periodic_box(40, 30), dict(nu=0.004, cfl=0.5)),
     "periodic_y_channel": (_periodic_y_channel, dict(nu=0.003, cfl=0.5)),
     "inlet_outlet_13x9": (lambda: meshgen.inlet_outlet_box(13, 9), dict(nu=0.005, cfl=0.5)),
     "half_channel_symmetry": (_half_channel, dict(nu=0.005, cfl=0.5)),
@@ -109,7 +113,8 @@ def test_window_against_oracle(sd, oracle_mod, name, scheme, macro):
 
 
 @pytest.mark.parametrize("prec", ["fp32dev", "fp32neq"])
-@pytest.mark.parametrize("name", ["cavity_23", "couette_4x32", "periodic_box_18x9", "inlet_outlet_13x9"])
+@pytest.mark.parametrize("name", ["cavity_23", "cavity_33", "cavity_40x40_lid", "couette_4x32", "periodic_box_18x9",
+                                  "periodic_box_40x30", "inlet_outlet_13x9"])
 def test_fp32_window_against_oracle(sd, oracle_mod, name, prec):
     """The FP32 storage forms on the structured step, 40 steps from a generic
     state, with the bars of the general step's FP32 windows (f and rho
