@@ -50,9 +50,10 @@ def test_unknown_section_is_refused():
     assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
     b = _bench()
     assert set(b.SECTIONS) == {"cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large",
-                               "serving_full"}
-    # the full-range serving trace runs only when named
-    assert "serving_full" not in b.DEFAULT_SECTIONS
+                               "serving_narrow"}
+    # the narrower serving trace runs only when named
+    assert "serving_narrow" not in b.DEFAULT_SECTIONS
+    assert b.SERVING_TRACE["cavity_n"] == (64, 1024) and b.SERVING_TRACE["cylinder_cells"] == (10_000, 1_000_000)
 
 
 def test_cpu_model_is_named():
