@@ -75,6 +75,13 @@ constexpr int cYv[6] = {2, 4, 5, 6, 7, 8};
 // position of velocity i among them (-1: none)
 constexpr int cXk[9] = {-1, 0, -1, 1, -1, 2, 3, 4, 5};
 constexpr int cYk[9] = {-1, -1, 0, -1, 1, 2, 3, 4, 5};
+constexpr bool positions_match()
+{
+    for (int k = 0; k < 6; k++)
+        if (cXk[cXv[k]] != k || cYk[cYv[k]] != k || cEx[cXv[k]] == 0 || cEy[cYv[k]] == 0) return false;
+    return true;
+}
+static_assert(positions_match(), "velocity positions along the axes");
 
 // Element i of a row that starts at base, addressed as base + a 32-bit byte
 // offset: the base stays a scalar and the lanes add one unsigned offset (the
@@ -129,8 +136,8 @@ __device__ __forceinline__ void face_flux(const DevMesh &m, const typename Shape
     using R = typename S::R;
     constexpr bool DEV = PM == SDUGKS_FP32DEV;
     const R rdt = (R)m.dtr, rc1 = (R)m.fc1, rbf = (R)m.fb;
-    // reconstruction offsets along the normal from each centre: h - e_n dt
-    const R lom = (R)hlo - rdt, lop = (R)hlo + rdt, him = (R)hhi - rdt, hip = (R)hhi + rdt;
+    // reconstruction offsets along the normal from the upwind centre: h - e_n dt
+    const R lom = (R)hlo - rdt, hip = (R)hhi + rdt;
     // boundary state of a wall face, seen from its fluid cell
     double rb = 0, ub = 0, vb = 0, rin = 0, uin = 0, vin = 0;
     const int inb = wall < 0 ? hib : lob, ini = wall < 0 ? hii : loi;
