@@ -285,8 +285,8 @@ void release_step_graphs(sdugks_t *h)
 {
     for (int c = 0; c < 2; c++)
         for (int k = 0; k < 2; k++) {
-            if (h->exec[c][k]) hipGraphExecDestroy(h->exec[c][k]);
-            if (h->graph[c][k]) hipGraphDestroy(h->graph[c][k]);
+            if (h->exec[c][k]) (void)hipGraphExecDestroy(h->exec[c][k]);
+            if (h->graph[c][k]) (void)hipGraphDestroy(h->graph[c][k]);
             h->exec[c][k] = nullptr;
             h->graph[c][k] = nullptr;
         }
@@ -306,10 +306,10 @@ int capture_step_graph(sdugks_t *h, int c, int64_t pairs, hipGraph_t &graph, hip
         rc = launch_step_at(h, c, h->stream, &gc);
         if (!rc) rc = launch_step_at(h, c ^ 1, h->stream, &gc);
     }
-    if (rc) { hipGraphDestroy(gr); return rc; }
+    if (rc) { (void)hipGraphDestroy(gr); return rc; }
     const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
-        hipGraphDestroy(gr);
+        (void)hipGraphDestroy(gr);
         exec = nullptr;
         return fail(SDUGKS_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ie));
     }
@@ -381,7 +381,7 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
     if (rc) { delete h; return rc; }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) { delete h; return fail(SDUGKS_ENODEV, "no HIP device"); }
-    hipGetDevice(&h->device);
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return fail(SDUGKS_ENODEV, "no current HIP device"); }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, h->device) != hipSuccess || std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
         delete h;
@@ -406,15 +406,15 @@ int sdugks_create(const sdugks_mesh *mesh, const sdugks_bc *bc, int32_t n_bc, co
         h->own = true;
     }
     if (hipHostMalloc((void **)&h->host4, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        if (h->own) hipFree(h->base);
+        if (h->own) (void)hipFree(h->base);
         delete h;
         return fail(SDUGKS_ENOMEM, "pinned host allocation failed");
     }
     const MeshBuild &mb = h->mb;
     const size_t nc = mb.nc, np = L.np;
     auto cleanup = [&](int code) {
-        if (h->own) hipFree(h->base);
-        hipHostFree(h->host4);
+        if (h->own) (void)hipFree(h->base);
+        (void)hipHostFree(h->host4);
         delete h;
         return code;
     };
@@ -811,7 +811,7 @@ int sdugks_step_profiled(sdugks_t *h, int64_t n, double *avg_ms, const char **na
     const int nk = tiled ? 1 : 2;
     struct Events {                       // destroyed on every return path
         hipEvent_t e[3] = {nullptr, nullptr, nullptr};
-        ~Events() { for (hipEvent_t x : e) if (x) hipEventDestroy(x); }
+        ~Events() { for (hipEvent_t x : e) if (x) (void)hipEventDestroy(x); }
     } evs;
     hipEvent_t *ev = evs.e;
     for (int k = 0; k < 3; k++) HIPCHK(hipEventCreate(&ev[k]));
@@ -901,11 +901,11 @@ int sdugks_info(sdugks_t *h, double *dt, double *tau, int64_t *step, int32_t *n_
 int sdugks_destroy(sdugks_t *h)
 {
     if (!h) return SDUGKS_OK;
-    hipSetDevice(h->device);
-    hipStreamSynchronize(h->stream);
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
     release_step_graphs(h);
-    if (h->own) hipFree(h->base);
-    hipHostFree(h->host4);
+    if (h->own) (void)hipFree(h->base);
+    (void)hipHostFree(h->host4);
     delete h;
     return SDUGKS_OK;
 }
@@ -934,10 +934,10 @@ size_t next_pow2(size_t x)
 
 void batch_release_graph(sdugks_batch_t *b)
 {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->exec_k) hipGraphExecDestroy(b->exec_k);
-    if (b->graph_k) hipGraphDestroy(b->graph_k);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_k) (void)hipGraphExecDestroy(b->exec_k);
+    if (b->graph_k) (void)hipGraphDestroy(b->graph_k);
     b->exec = nullptr;
     b->graph = nullptr;
     b->exec_k = nullptr;
@@ -947,8 +947,8 @@ void batch_release_graph(sdugks_batch_t *b)
 void batch_release_groups(sdugks_batch_t *b)
 {
     for (auto &g : b->groups) {
-        hipFree(g.d_inst);
-        hipFree(g.d_tmap);
+        (void)hipFree(g.d_inst);
+        (void)hipFree(g.d_tmap);
     }
     b->groups.clear();
 }
@@ -995,8 +995,8 @@ int batch_build_tables(sdugks_batch_t *b)
             if (hipMalloc((void **)&g.d_inst, g.cap_inst * sizeof(BatchInst)) != hipSuccess ||
                 hipMalloc((void **)&g.d_tmap, batch_grid(g.cap_tiles) * sizeof(int2)) != hipSuccess) {
                 for (auto &x : want) {
-                    if (x.d_inst) hipFree(x.d_inst);
-                    if (x.d_tmap) hipFree(x.d_tmap);
+                    if (x.d_inst) (void)hipFree(x.d_inst);
+                    if (x.d_tmap) (void)hipFree(x.d_tmap);
                 }
                 return fail(SDUGKS_ENOMEM, "hipMalloc of a batch table failed");
             }
@@ -1165,10 +1165,10 @@ int batch_capture(sdugks_batch_t *b, int64_t pairs, hipGraph_t &graph, hipGraphE
         rc = batch_launch(b, 0, &gc);
         if (!rc) rc = batch_launch(b, 1, &gc);
     }
-    if (rc) { hipGraphDestroy(gr); return rc; }
+    if (rc) { (void)hipGraphDestroy(gr); return rc; }
     const hipError_t ie = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
-        hipGraphDestroy(gr);
+        (void)hipGraphDestroy(gr);
         exec = nullptr;
         return fail(SDUGKS_EHIP, std::string("graph instantiation: ") + hipGetErrorString(ie));
     }
@@ -1232,7 +1232,7 @@ int sdugks_batch_residual(sdugks_batch_t *b, double *eps)
     HIPCHK(hipSetDevice(b->device));
     if (n > b->cap_jobs) {
         HIPCHK(hipStreamSynchronize(b->stream));
-        hipHostFree(b->h_jobs); hipFree(b->d_jobs); hipHostFree(b->h_out); hipFree(b->d_out);
+        (void)hipHostFree(b->h_jobs); (void)hipFree(b->d_jobs); (void)hipHostFree(b->h_out); (void)hipFree(b->d_out);
         b->h_jobs = nullptr; b->d_jobs = nullptr; b->h_out = nullptr; b->d_out = nullptr;
         b->cap_jobs = 0;
         const size_t cap = next_pow2((size_t)n);
@@ -1328,16 +1328,16 @@ int sdugks_debug_batch_fail(sdugks_batch_t *b)
 int sdugks_batch_destroy(sdugks_batch_t *b)
 {
     if (!b) return SDUGKS_OK;
-    hipSetDevice(b->device);
-    if (b->stream) hipStreamSynchronize(b->stream);
-    hipHostFree(b->h_jobs);
-    hipFree(b->d_jobs);
-    hipHostFree(b->h_out);
-    hipFree(b->d_out);
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    (void)hipHostFree(b->h_jobs);
+    (void)hipFree(b->d_jobs);
+    (void)hipHostFree(b->h_out);
+    (void)hipFree(b->d_out);
     batch_release_graph(b);
     batch_release_groups(b);
-    if (b->ev) hipEventDestroy(b->ev);
-    if (b->own_stream) hipStreamDestroy(b->stream);
+    if (b->ev) (void)hipEventDestroy(b->ev);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return SDUGKS_OK;
 }

@@ -46,7 +46,10 @@ hipError_t noalloc_scratch(int device, double **out)
         if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
         void *p = nullptr;
         e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
-        if (cur != device) hipSetDevice(cur);
+        if (cur != device) {
+            const hipError_t back = hipSetDevice(cur);   // the caller's device, as it was
+            if (e == hipSuccess) e = back;
+        }
         if (e != hipSuccess) return e;
         g_ptr[device] = p;
     }
