@@ -395,19 +395,21 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
     from rest and the 200,000-triangle cylinder at Re 40 from the free stream,
     each in FP64 until the velocity residual (checked every 1000 steps) falls
     below 1e-8, with the two FP32 storage forms of the same case advanced
-    alongside, each on a stream of its own, for the same number of steps (a
-    form stops earlier only if it reaches the tolerance itself).  Reported:
-    steps, wall time, final residual and mass drift of each, and each FP32
-    form's velocity error (relative L2 and L-infinity over cells) against the
-    converged FP64 field, with its residual at the end (median of its last ten
-    checks)."""
+    alongside, each on a stream of its own.  The FP32 deviation form stops
+    with FP64 (or earlier, at the tolerance); the FP32 non-equilibrium form,
+    which has FP64 arithmetic, runs on to the tolerance itself, up to 1.5
+    times FP64's steps.  Reported: steps, wall time, final residual and mass
+    drift of each, whether it met the rule, and each FP32 form's velocity
+    error (relative L2 and L-infinity over cells) against the converged FP64
+    field; a form that stopped above the tolerance also gets its residual at
+    the end (median of its last ten checks)."""
     import numpy as np
     import torch
     cases = {"cavity256_re1000": (lambda: meshgen.cavity(256, beta=1.5, U=0.1), dict(nu=1e-4, cfl=0.5, structured=2)),
              "cylinder200k_re40": (lambda: meshgen.cylinder_ogrid(400, 250, seed=0),
                                    dict(nu=0.1 / 40, cfl=0.5, u0=0.1, tile_cells=64, block_threads=256))}
-    out = {"rule": f"velocity residual below {tol:g}, checked every {interval} steps (FP64); the FP32 storage "
-                   "forms run alongside for the same steps",
+    out = {"rule": f"velocity residual below {tol:g}, checked every {interval} steps; the FP32 deviation form "
+                   "runs alongside FP64 for its steps, the FP32 non-equilibrium form on to the rule (cap 1.5x FP64)",
            "cases": {}}
     for name, (build, kw) in cases.items():
         mesh, bcs = build()
@@ -433,7 +435,8 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
                     r["done"] = r["eps"] < tol or r["steps"] >= cap or math.isnan(r["eps"])
                 else:
                     f = runs["f64"]
-                    r["done"] = r["eps"] < tol or (f["done"] and r["steps"] >= f["steps"]) or math.isnan(r["eps"])
+                    limit = f["steps"] * (1.5 if pname == "fp32neq" else 1.0)
+                    r["done"] = r["eps"] < tol or (f["done"] and r["steps"] >= limit) or math.isnan(r["eps"])
                 if r["done"]:
                     r["t"] = time.perf_counter() - t0
             if time.perf_counter() - last > 15:
@@ -446,7 +449,8 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
             s = r["s"]
             rho, u, v = s.macros()
             uv[pname] = np.concatenate([u, v])
-            res[pname] = {"steps": r["steps"], "residual": float(f"{r['eps']:.3g}"), "wall_s": round(r["t"], 1),
+            res[pname] = {"steps": r["steps"], "residual": float(f"{r['eps']:.3g}"), "met_rule": bool(r["eps"] < tol),
+                          "wall_s": round(r["t"], 1),
                           "mass_drift": float(f"{(s.mass() - r['m0']) / r['m0']:.4g}"),
                           "ms_per_step_alongside": round(r["t"] * 1e3 / r["steps"], 5)}
             s.close()
@@ -454,7 +458,8 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
             d = uv[pname] - uv["f64"]
             res[pname]["velocity_rel_l2_vs_f64"] = float(f"{np.linalg.norm(d) / np.linalg.norm(uv['f64']):.3g}")
             res[pname]["velocity_rel_linf_vs_f64"] = float(f"{np.abs(d).max() / np.abs(uv['f64']).max():.3g}")
-            res[pname]["residual_floor"] = float(f"{np.median(runs[pname]['hist'][-10:]):.3g}")
+            if not res[pname]["met_rule"]:
+                res[pname]["residual_floor"] = float(f"{np.median(runs[pname]['hist'][-10:]):.3g}")
         res["cells"] = len(mesh["cell_ptr"]) - 1
         out["cases"][name] = res
         progress(f"converge {name}: f64 {res['f64']['steps']} steps, fp32dev error "
