@@ -390,6 +390,19 @@ def cylinder_form(meshgen, n_theta=200, n_r=125, tol=1e-8):
             "steady": rows, "unsteady": unsteady}
 
 
+def converge_done(pname, eps, steps, f64_done, f64_steps, tol, cap):
+    """Stopping rule of the converge section for one form after a check: FP64
+    stops at the tolerance or the cap; the FP32 deviation form at the
+    tolerance or once FP64 has stopped and it has run as many steps; the FP32
+    non-equilibrium form at the tolerance or at 1.5 times FP64's steps.  A
+    non-finite residual stops any form."""
+    if math.isnan(eps) or eps < tol:
+        return True
+    if pname == "f64":
+        return steps >= cap
+    return f64_done and steps >= f64_steps * (1.5 if pname == "fp32neq" else 1.0)
+
+
 def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_000_000):
     """The two stopping rules, run to the end: the 256 x 256 cavity at Re 1000
     from rest and the 200,000-triangle cylinder at Re 40 from the free stream,
@@ -431,12 +444,8 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
                 r["steps"] += interval
                 r["eps"] = r["s"].residual()
                 r["hist"].append(r["eps"])
-                if pname == "f64":
-                    r["done"] = r["eps"] < tol or r["steps"] >= cap or math.isnan(r["eps"])
-                else:
-                    f = runs["f64"]
-                    limit = f["steps"] * (1.5 if pname == "fp32neq" else 1.0)
-                    r["done"] = r["eps"] < tol or (f["done"] and r["steps"] >= limit) or math.isnan(r["eps"])
+                f = runs["f64"]
+                r["done"] = converge_done(pname, r["eps"], r["steps"], f["done"], f["steps"], tol, cap)
                 if r["done"]:
                     r["t"] = time.perf_counter() - t0
             if time.perf_counter() - last > 15:

@@ -77,3 +77,20 @@ def test_traffic_requires_the_recorded_schedule(tmp_path, monkeypatch):
     assert b.measured_traffic("w", {"tile_cells": 32, "block_threads": 128}) == 123
     assert b.measured_traffic("w", {"tile_cells": 16, "block_threads": 64}) is None
     assert b.measured_traffic("w") == 123
+
+
+def test_converge_stopping_rule():
+    """FP64 stops at the tolerance or the cap; the FP32 deviation form with
+    FP64; the FP32 non-equilibrium form runs on to the tolerance, up to 1.5
+    times FP64's steps; a non-finite residual stops every form."""
+    done = _bench().converge_done
+    assert done("f64", 9e-9, 1000, False, 0, 1e-8, 10**6)
+    assert not done("f64", 2e-8, 1000, False, 0, 1e-8, 10**6)
+    assert done("f64", 2e-8, 10**6, False, 0, 1e-8, 10**6)
+    assert not done("fp32dev", 4e-8, 2000, False, 1000, 1e-8, 10**6)
+    assert done("fp32dev", 4e-8, 2000, True, 2000, 1e-8, 10**6)
+    assert not done("fp32neq", 2e-8, 2000, True, 2000, 1e-8, 10**6)
+    assert not done("fp32neq", 2e-8, 2999, True, 2000, 1e-8, 10**6)
+    assert done("fp32neq", 2e-8, 3000, True, 2000, 1e-8, 10**6)
+    assert done("fp32neq", 9e-9, 2100, True, 2000, 1e-8, 10**6)
+    assert all(done(p, float("nan"), 1, False, 0, 1e-8, 10**6) for p in ("f64", "fp32dev", "fp32neq"))
