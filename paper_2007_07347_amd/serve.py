@@ -26,6 +26,11 @@ state with the same FP32 storage and FP64 arithmetic (FP32NEQ), which has
 no such floor (the floor comes from the FP32 face arithmetic), when the new
 instance fits the remaining budget.
 
+A request whose instance cannot be made (the library rejects its mesh or
+parameters, or the memory runs out) is retired as "failed" with the error's
+text, and its bytes return to the budget; the others are served as before.
+A failed escalation leaves the request in its first form.
+
 Time-to-steady of a request = completion time - arrival time (queueing
 included).  The backend interface keeps the policy testable without a GPU:
 
@@ -65,13 +70,14 @@ class Result:
     rid: int
     kind: str
     n_cells: int
-    status: str                     # "converged", "not_converged", "diverged", "rejected"
+    status: str                     # "converged", "not_converged", "diverged", "rejected", "failed"
     arrival: float
     admitted: float
     finished: float
     steps: int
     residual: float
     macros: Optional[tuple] = None
+    error: str = ""                 # "failed": why the instance could not be made
 
     @property
     def time_to_steady(self):
@@ -141,20 +147,35 @@ class Server:
                 self.log.append((now(), "admit", req.rid, need))
                 if make_async is not None:
                     staging.append([req, make_async(req), need, now()])
-                else:
-                    active.append([req, self.backend.create(req), need, now(), 0, math.inf, 0, False])
-                    members_changed = True
+                    continue
+                try:
+                    inst = self.backend.create(req)
+                except Exception as e:          # this request only: its bytes return to the budget
+                    used -= need
+                    self._fail(results, req, now(), e)
+                    continue
+                active.append([req, inst, need, now(), 0, math.inf, 0, False])
+                members_changed = True
             # instances made on the worker join at this chunk boundary; with
             # nothing running, wait for the first one instead of spinning
             if staging and not active:
-                staging[0][1].result()
+                try:
+                    staging[0][1].result()
+                except Exception:               # handled with the others below
+                    pass
             still = []
             for st in staging:
-                if st[1].done():
-                    active.append([st[0], st[1].result(), st[2], st[3], 0, math.inf, 0, False])
-                    members_changed = True
-                else:
+                if not st[1].done():
                     still.append(st)
+                    continue
+                try:
+                    inst = st[1].result()
+                except Exception as e:
+                    used -= st[2]
+                    self._fail(results, st[0], now(), e)
+                    continue
+                active.append([st[0], inst, st[2], st[3], 0, math.inf, 0, False])
+                members_changed = True
             staging = still
             if not active:
                 if pending:
@@ -206,7 +227,12 @@ class Server:
                     else:
                         a[6] += 1
                     if can_escalate and not a[7] and a[6] >= self.stall_checks:
-                        got = self.backend.escalate(req, inst, self.budget - used + need)
+                        try:
+                            got = self.backend.escalate(req, inst, self.budget - used + need)
+                        except Exception as e:  # keep serving it in its first form
+                            got = None
+                            a[7] = True
+                            self.log.append((now(), "escalate_failed", req.rid, str(e)))
                         if got is not None:
                             new, new_need = got
                             used += new_need - need
@@ -235,6 +261,11 @@ class Server:
         out = [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
         return out, summarize(out, elapsed, cell_updates)
 
+    def _fail(self, results, req, t, e):
+        results[req.rid] = Result(req.rid, req.kind, req.n_cells, "failed", req.arrival, t, t, 0, math.inf,
+                                  error=str(e))
+        self.log.append((t, "failed", req.rid, str(e)))
+
 
 def summarize(results, elapsed, cell_updates):
     done = [r for r in results if r.status == "converged"]
@@ -249,6 +280,7 @@ def summarize(results, elapsed, cell_updates):
             "not_converged": sum(r.status == "not_converged" for r in results),
             "diverged": sum(r.status == "diverged" for r in results),
             "rejected": sum(r.status == "rejected" for r in results),
+            "failed": sum(r.status == "failed" for r in results),
             "p50_time_to_steady_s": pct(50), "p99_time_to_steady_s": pct(99),
             "makespan_s": elapsed, "cell_updates": cell_updates,
             "aggregate_mlups": cell_updates / elapsed / 1e6 if elapsed > 0 else None}
@@ -273,7 +305,11 @@ class SequentialServer(Server):
                                           math.inf)
                 continue
             t_adm = now()
-            inst = self.backend.create(req)
+            try:
+                inst = self.backend.create(req)
+            except Exception as e:
+                self._fail(results, req, now(), e)
+                continue
             steps, status, eps = 0, None, math.inf
             while status is None:
                 inst.step(self.interval)
@@ -355,7 +391,11 @@ class GpuBackend:
         if need > room:
             return None
         new = self.sd.Solver(req.mesh, req.bcs, stream=getattr(inst, "stream", None), **kw)
-        new.set_state(*inst.state())
+        try:
+            new.set_state(*inst.state())
+        except Exception:
+            new.close()
+            raise
         return new, need
 
     def close(self):

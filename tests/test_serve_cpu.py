@@ -365,3 +365,83 @@ def test_async_admission_overlaps_the_running_batch():
     t_admit = {rid: t for t, ev, rid, _ in srv.log if ev == "admit"}
     assert t_admit[3] >= min(res[1].finished, res[2].finished)   # 3 waited for budget, FIFO
     assert all(inst.closed for inst in be.live.values())
+
+
+# ---- a request whose instance cannot be made fails alone
+class FailingBackend(AsyncBackend):
+    """create() raises for requests marked "bad" (as the library does for a
+    mesh it rejects); create_async() hands the error over through the future."""
+
+    def __init__(self, clock, use_async):
+        super().__init__(clock)
+        self.use_async = use_async
+        if not use_async:
+            self.create_async = None
+
+    def create(self, req):
+        if req.params.get("bad"):
+            e = ValueError(f"mesh of request {req.rid} rejected")
+            e.code = -1
+            raise e
+        return super().create(req)
+
+    def batch(self, instances):
+        return FakeBatch(instances, self.clock, self.log)
+
+
+class FailedFuture(SimFuture):
+    def __init__(self, clock, ready_at, err):
+        super().__init__(clock, ready_at, None)
+        self.err = err
+
+    def result(self):
+        super().result()
+        raise self.err
+
+
+@pytest.mark.parametrize("use_async", [False, True])
+def test_failed_creation_isolated_and_budget_returned(use_async):
+    clock = SimClock()
+    be = FailingBackend(clock, use_async)
+    if use_async:
+        def create_async(req):
+            try:
+                inst = be.create(req)
+            except ValueError as e:
+                return FailedFuture(clock, clock.t + 0.01, e)
+            return SimFuture(clock, clock.t + 0.01, inst)
+        be.create_async = create_async
+    # the budget holds one request at a time: the failed one must give its bytes back
+    specs = [(0.0, 10, {"need": 2000, "bad": True}), (0.0, 10, {"need": 2000}), (0.0, 10, {"need": 1000, "bad": True}),
+             (0.0, 10, {"need": 1000})]
+    srv = Server(be, budget_bytes=1000, clock=clock, sleep=clock.sleep, interval=1000)
+    res, stats = srv.run(reqs(specs))
+    assert [r.status for r in res] == ["failed", "converged", "failed", "converged"]
+    assert "rejected" in res[0].error and res[1].error == ""
+    assert stats["failed"] == 2 and stats["converged"] == 2
+    assert all(inst.closed for inst in be.live.values())
+
+
+def test_failed_creation_in_the_sequential_loop():
+    clock = SimClock()
+    be = FailingBackend(clock, use_async=False)
+    srv = SequentialServer(be, budget_bytes=10**6, clock=clock, sleep=clock.sleep, interval=1000)
+    res, stats = srv.run(reqs([(0.0, 10, {"need": 1000, "bad": True}), (0.0, 10, {"need": 1000})]))
+    assert [r.status for r in res] == ["failed", "converged"]
+
+
+def test_failed_escalation_keeps_the_first_form():
+    """An escalation that raises leaves the request in its first form, not
+    escalated again, and it runs on to the step cap."""
+    clock = SimClock()
+    be = EscalatingBackend(clock)
+
+    def boom(req, inst, room):
+        raise MemoryError("no room on the device")
+    be.escalate = boom
+    srv = Server(be, budget_bytes=10**6, clock=clock, sleep=clock.sleep, interval=1000, tol=1e-7,
+                 stall_checks=4, step_cap=20_000)
+    res, stats = srv.run(reqs([(0.0, 100, {})]))
+    assert [r.status for r in res] == ["not_converged"]
+    assert sum(ev == "escalate_failed" for _, ev, _, _ in srv.log) == 1
+    assert all(inst.closed for inst in be.live.values())
