@@ -153,21 +153,22 @@ def test_batch_autotuner_times_every_candidate(sd, tmp_path):
     assert autotune.label(best) in {autotune.label(r) for r in table}
 
 
-@pytest.mark.parametrize("sched", [(64, 256), (32, 128)])
+@pytest.mark.parametrize("sched", ["structured", (64, 256), (32, 128)])
 def test_full_size_64_cavity_batch(sd, oracle_mod, sched):
     """The batched workload at its full size (64 tanh cavities, edges
     log-uniform in [32, 512], Re uniform in [100, 5000], seed 2026, FP32
     deviation storage, 2.29M cells) on the schedules the batch autotuner
-    chooses between: 30 batched steps give the same bits as each member
+    chooses between (the structured step, which it picks, and the general
+    step's best two): 30 batched steps give the same bits as each member
     stepped alone, and the two smallest members, sampled against the FP64
     oracle, stay within the FP32 deviation form's window bar."""
     rng = np.random.default_rng(2026)
     sizes = meshgen.log_uniform_int(rng, 32, 512, size=64)
     res = rng.uniform(100.0, 5000.0, size=64)
-    tc, bt = sched
+    sk = dict(structured=2) if sched == "structured" else dict(tile_cells=sched[0], block_threads=sched[1])
     problems = [(meshgen.cavity(int(n), beta=1.5, U=0.1), dict(nu=0.1 / re, cfl=0.5)) for n, re in zip(sizes, res)]
     assert sum(int(n) ** 2 for n in sizes) == 2289523
-    mk = lambda: [sd.Solver(m, b, precision=sd.FP32DEV, tile_cells=tc, block_threads=bt, **kw)
+    mk = lambda: [sd.Solver(m, b, precision=sd.FP32DEV, **sk, **kw)
                   for (m, b), kw in problems]
     alone, batched = mk(), mk()
     for s in alone:

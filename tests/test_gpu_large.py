@@ -1,6 +1,7 @@
 """Parity at the large launch configuration: the 2048 x 2048 tanh cavity
-(4.2M cells, working set above 2 GB) on 64-cell tiles and 256 threads, the
-shape the bench times, against the oracle on sampled cells.
+(4.2M cells, working set above 0.8 GB) on both steps the bench times there
+(the general step on 64-cell tiles and 256 threads, and the structured step
+on its 16 x 14 or 16 x 7 tiles), against the oracle on sampled cells.
 
 The oracle cannot step 4.2M cells in a test, but one step of a cell depends
 only on the state of the cells within two faces of it (its own and its
@@ -30,7 +31,8 @@ def sd():
 def samples(n, seed=11, n_interior=6):
     rng = np.random.default_rng(seed)
     fixed = [(0, 0), (n - 1, 0), (0, n - 1), (n - 1, n - 1), (n // 2, 0), (0, n // 2), (n - 1, n // 2),
-             (n // 2, n - 1), (1, 1), (n - 2, n - 2), (63, 64), (64, 63)]
+             (n // 2, n - 1), (1, 1), (n - 2, n - 2), (63, 64), (64, 63),
+             (15, 14), (16, 13), (32, 7), (33, 6)]      # tile corners of both steps
     rand = [tuple(int(x) for x in rng.integers(2, n - 2, size=2)) for _ in range(n_interior)]
     return fixed + rand
 
@@ -80,11 +82,13 @@ def test_window_step_equals_full_step(oracle_mod):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("step", ["general", "structured"])
 @pytest.mark.parametrize("precision,bar", [("FP64", 1e-12), ("FP32DEV", 2e-6)])
-def test_cavity_2048_sampled_cells(sd, oracle_mod, precision, bar):
+def test_cavity_2048_sampled_cells(sd, oracle_mod, precision, bar, step):
     mesh, bcs = meshgen.cavity(N)
     xs = meshgen.tanh_nodes(N)
-    g = sd.Solver(mesh, bcs, nu=NU, cfl=0.5, precision=getattr(sd, precision), tile_cells=64, block_threads=256)
+    sched = dict(tile_cells=64, block_threads=256) if step == "general" else dict(structured=2)
+    g = sd.Solver(mesh, bcs, nu=NU, cfl=0.5, precision=getattr(sd, precision), **sched)
     assert g.n_cells == N * N
     f0, W0, _ = meshgen.random_state(g.n_cells, seed=17, amp=0.02)
     g.set_state(f0, W0)
@@ -105,4 +109,4 @@ def test_cavity_2048_sampled_cells(sd, oracle_mod, precision, bar):
         ew = np.abs(W1[gid[c]] - Wo[c]).max() / np.abs(Wo[c]).max()
         worst = max(worst, ef, ew)
         assert ef <= bar and ew <= bar, ((i0, j0), ef, ew)
-    print(precision, "worst sampled relative error", f"{worst:.2e}", flush=True)
+    print(precision, step, "worst sampled relative error", f"{worst:.2e}", flush=True)
