@@ -774,6 +774,7 @@ def main():
         print(json.dumps({"large": large_form(sdugks, meshgen)}), flush=True)
         return
 
+    t_start = time.perf_counter()
     hb = batch_headline(sdugks, autotune, meshgen, a)
     cells, ms = hb["cells"], hb["ms"]
     mlups = cells * a.steps / (ms / 1e3) / 1e6
@@ -814,27 +815,36 @@ def main():
                                        for r in hb["table"]},
     }
     sections = set() if a.no_extra else {x for x in a.sections.split(",") if x}
+    section_s = {"headline": round(time.perf_counter() - t_start, 1)}
+
+    def run(name, key, fn):
+        # each section's wall time (set-up, autotuning and its own timed runs)
+        t0 = time.perf_counter()
+        out[key] = fn()
+        section_s[name] = round(time.perf_counter() - t0, 1)
+        progress(f"{name} done in {section_s[name]} s")
     if "cavity256" in sections:
-        out["cavity256"] = cavity256_form(sdugks, autotune, meshgen, a)
+        run("cavity256", "cavity256", lambda: cavity256_form(sdugks, autotune, meshgen, a))
     if "converge" in sections:
-        out["converge"] = converge_form(sdugks, meshgen)
+        run("converge", "converge", lambda: converge_form(sdugks, meshgen))
     if "serving" in sections:
-        out["serving"] = serving(meshgen)
-        progress("serving trace done")
+        run("serving", "serving", lambda: serving(meshgen))
     if "serving_narrow" in sections:
-        out["serving_narrow"] = serving(meshgen, step_cap=300_000, trace_kw=SERVING_TRACE_NARROW)
-        progress("narrow serving trace done")
+        run("serving_narrow", "serving_narrow",
+            lambda: serving(meshgen, step_cap=300_000, trace_kw=SERVING_TRACE_NARROW))
     if "cylinder" in sections:
-        out["cylinder"] = cylinder_form(meshgen)
+        run("cylinder", "cylinder", lambda: cylinder_form(meshgen))
     if "original" in sections:
-        out["original_scheme"] = original_scheme_form(sdugks, meshgen, out.get("cavity256", {}).get(
-            "f64", {}).get("schedule", {"tile_cells": 32, "block_threads": 128}))
+        run("original", "original_scheme", lambda: original_scheme_form(sdugks, meshgen, out.get("cavity256", {}).get(
+            "f64", {}).get("schedule", {"tile_cells": 32, "block_threads": 128})))
     if "cylinder200k" in sections:
-        out["cylinder200k"] = cylinder200k_form(sdugks, autotune, meshgen, schedule=a.cylinder_schedule)
+        run("cylinder200k", "cylinder200k",
+            lambda: cylinder200k_form(sdugks, autotune, meshgen, schedule=a.cylinder_schedule))
     if "large" in sections:
-        out["large"] = large_form(sdugks, meshgen)
+        run("large", "large", lambda: large_form(sdugks, meshgen))
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(meshgen, a.cpu_seconds)
+        run("cpu_baseline", "cpu_baseline", lambda: cpu_baseline(meshgen, a.cpu_seconds))
+    out["section_wall_s"] = section_s
     print(json.dumps(out), flush=True)
 
 
