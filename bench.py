@@ -59,9 +59,12 @@ KERNEL_SOURCES = {
     "k_step_batch_cart": ("step_cart.hip", "step_common.h"),
 }
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
-SECTIONS = ("cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large", "serving_narrow")
-# the narrower serving trace (smaller meshes, longer cap) runs only when named
-DEFAULT_SECTIONS = SECTIONS[:-1]
+SECTIONS = ("cavity256", "converge", "serving", "cylinder200k", "original", "large",
+            "converge_cylinder", "cylinder", "serving_narrow")
+# Run only when named, so that the default run stays within a few minutes:
+# the 200k cylinder to its stopping rule (about 2.7M steps, two minutes),
+# the cylinder physics (Re 10 to 100) and the narrower serving trace
+DEFAULT_SECTIONS = SECTIONS[:6]
 
 
 def parse():
@@ -403,10 +406,13 @@ def converge_done(pname, eps, steps, f64_done, f64_steps, tol, cap):
     return f64_done and steps >= f64_steps * (1.5 if pname == "fp32neq" else 1.0)
 
 
-def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_000_000):
-    """The two stopping rules, run to the end: the 256 x 256 cavity at Re 1000
-    from rest and the 200,000-triangle cylinder at Re 40 from the free stream,
-    each in FP64 until the velocity residual (checked every 1000 steps) falls
+CONVERGE_CASES = ("cavity256_re1000", "cylinder200k_re40")
+
+
+def converge_form(sdugks, meshgen, names=CONVERGE_CASES, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_000_000):
+    """The two stopping rules, run to the end (`names` chooses): the 256 x 256
+    cavity at Re 1000 from rest and the 200,000-triangle cylinder at Re 40
+    from the free stream, each in FP64 until the velocity residual (checked every 1000 steps) falls
     below 1e-8, with the two FP32 storage forms of the same case advanced
     alongside, each on a stream of its own.  The FP32 deviation form stops
     with FP64 (or earlier, at the tolerance); the FP32 non-equilibrium form,
@@ -424,7 +430,8 @@ def converge_form(sdugks, meshgen, tol=1e-8, interval=RESIDUAL_INTERVAL, cap=8_0
     out = {"rule": f"velocity residual below {tol:g}, checked every {interval} steps; the FP32 deviation form "
                    "runs alongside FP64 for its steps, the FP32 non-equilibrium form on to the rule (cap 1.5x FP64)",
            "cases": {}}
-    for name, (build, kw) in cases.items():
+    for name in names:
+        build, kw = cases[name]
         mesh, bcs = build()
         runs = {}
         for prec, pname in ((sdugks.FP64, "f64"), (sdugks.FP32DEV, "fp32dev"), (sdugks.FP32NEQ, "fp32neq")):
@@ -826,7 +833,9 @@ def main():
     if "cavity256" in sections:
         run("cavity256", "cavity256", lambda: cavity256_form(sdugks, autotune, meshgen, a))
     if "converge" in sections:
-        run("converge", "converge", lambda: converge_form(sdugks, meshgen))
+        run("converge", "converge", lambda: converge_form(sdugks, meshgen, names=CONVERGE_CASES[:1]))
+    if "converge_cylinder" in sections:
+        run("converge_cylinder", "converge_cylinder", lambda: converge_form(sdugks, meshgen, names=CONVERGE_CASES[1:]))
     if "serving" in sections:
         run("serving", "serving", lambda: serving(meshgen))
     if "serving_narrow" in sections:

@@ -50,9 +50,10 @@ def test_unknown_section_is_refused():
     assert r.returncode == 2 and "unknown sections: ['nope']" in r.stderr
     b = _bench()
     assert set(b.SECTIONS) == {"cavity256", "converge", "serving", "cylinder", "cylinder200k", "original", "large",
-                               "serving_narrow"}
-    # the narrower serving trace runs only when named
-    assert "serving_narrow" not in b.DEFAULT_SECTIONS
+                               "converge_cylinder", "serving_narrow"}
+    # the long sections run only when named, so the default run stays short
+    assert set(b.SECTIONS) - set(b.DEFAULT_SECTIONS) == {"converge_cylinder", "cylinder", "serving_narrow"}
+    assert b.CONVERGE_CASES == ("cavity256_re1000", "cylinder200k_re40")
     assert b.SERVING_TRACE["cavity_n"] == (64, 1024) and b.SERVING_TRACE["cylinder_cells"] == (10_000, 1_000_000)
 
 
