@@ -257,7 +257,8 @@ def batch_headline(sdugks, autotune, meshgen, a, seed=2026, n_inst=64):
     ws = sum(s.workspace.numel() for s in solvers)
     stream = torch.cuda.Stream()
     b = sdugks.Batch(solvers, stream=stream)
-    # the warm-up replays both captured graphs (32 and 2 steps) and the odd step
+    # the warm-up captures the batch's graphs (2 to 32 steps, all at the first call) and
+    # replays the longest and the shortest, then the odd step
     b.step(max(35, a.warmup))
     b.residuals()
     torch.cuda.synchronize()

@@ -34,6 +34,8 @@ constexpr size_t kAlign = 256;
 // Steps per replay of the long step graphs, in pairs (each pair returns every
 // instance to its buffer index).
 constexpr int64_t kGraphPairs = 16;
+constexpr int kBatchGraphs = 5;   // 2^(kBatchGraphs - 1) = kGraphPairs
+static_assert((int64_t)1 << (kBatchGraphs - 1) == kGraphPairs, "batch graph lengths");
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -168,10 +170,10 @@ struct sdugks_batch_s {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipEvent_t ev = nullptr;
-    hipGraph_t graph = nullptr;       // one pair of steps
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph_k = nullptr;     // kGraphPairs pairs of steps
-    hipGraphExec_t exec_k = nullptr;
+    // graphs of 1, 2, 4, .. kGraphPairs pairs of steps: a step count is
+    // replayed as runs of the longest plus one graph per set bit of the rest
+    hipGraph_t graph[kBatchGraphs] = {};
+    hipGraphExec_t exec[kBatchGraphs] = {};
     int device = 0;
     std::vector<int> cur_at_fill;     // members' buffer indices when the tables were filled
     bool failed = false;              // a table rebuild failed: no members until set_members succeeds
@@ -934,14 +936,12 @@ size_t next_pow2(size_t x)
 
 void batch_release_graph(sdugks_batch_t *b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->exec_k) (void)hipGraphExecDestroy(b->exec_k);
-    if (b->graph_k) (void)hipGraphDestroy(b->graph_k);
-    b->exec = nullptr;
-    b->graph = nullptr;
-    b->exec_k = nullptr;
-    b->graph_k = nullptr;
+    for (int k = 0; k < kBatchGraphs; k++) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
 }
 
 void batch_release_groups(sdugks_batch_t *b)
@@ -1084,15 +1084,20 @@ int batch_launch(sdugks_batch_t *b, int parity, GraphChain *gc = nullptr)
 // streams after the batch stream (after).
 int batch_join(sdugks_batch_t *b, bool before)
 {
+    // each distinct member stream once: members usually share one stream, and
+    // a record and a wait per member kept the host busy (and the batch
+    // stream idle) for about 13 us per member before the first step
+    std::vector<hipStream_t> seen;
     for (sdugks_t *h : b->members) {
-        if (h->stream == b->stream) continue;
+        if (h->stream == b->stream || std::find(seen.begin(), seen.end(), h->stream) != seen.end()) continue;
         if (before) {
             HIPCHK(hipEventRecord(b->ev, h->stream));
             HIPCHK(hipStreamWaitEvent(b->stream, b->ev, 0));
         } else {
-            HIPCHK(hipEventRecord(b->ev, b->stream));
+            if (seen.empty()) HIPCHK(hipEventRecord(b->ev, b->stream));
             HIPCHK(hipStreamWaitEvent(h->stream, b->ev, 0));
         }
+        seen.push_back(h->stream);
     }
     return SDUGKS_OK;
 }
@@ -1195,20 +1200,19 @@ int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
         }
     int rc = batch_join(b, true);
     if (rc) return rc;
-    // whole runs of kGraphPairs pairs replay the long graph (the gap the
-    // runtime leaves between two graph launches is then paid once per run),
-    // the remaining pairs the one-pair graph
+    // whole runs of kGraphPairs pairs replay the longest graph, the remaining
+    // pairs one graph per set bit (the runtime leaves a gap of several us
+    // between two graph launches, so few launches matter for short calls);
+    // all lengths are captured together at the first call that needs one
     int64_t pairs = n / 2;
     const int64_t runs = pairs / kGraphPairs;
     pairs -= runs * kGraphPairs;
-    if (runs > 0) {
-        if (!b->exec_k && (rc = batch_capture(b, kGraphPairs, b->graph_k, b->exec_k))) return rc;
-        for (int64_t k = 0; k < runs; k++) HIPCHK(hipGraphLaunch(b->exec_k, b->stream));
-    }
-    if (pairs > 0) {
-        if (!b->exec && (rc = batch_capture(b, 1, b->graph, b->exec))) return rc;
-        for (int64_t k = 0; k < pairs; k++) HIPCHK(hipGraphLaunch(b->exec, b->stream));
-    }
+    if (runs > 0 || pairs > 0)
+        for (int k = 0; k < kBatchGraphs; k++)
+            if (!b->exec[k] && (rc = batch_capture(b, (int64_t)1 << k, b->graph[k], b->exec[k]))) return rc;
+    for (int64_t k = 0; k < runs; k++) HIPCHK(hipGraphLaunch(b->exec[kBatchGraphs - 1], b->stream));
+    for (int k = kBatchGraphs - 2; k >= 0; k--)
+        if (pairs & ((int64_t)1 << k)) HIPCHK(hipGraphLaunch(b->exec[k], b->stream));
     if (n & 1) {
         rc = batch_launch(b, 0);
         if (rc) return rc;
