@@ -261,6 +261,14 @@ int sdugks_batch_create(sdugks_t *const *members, int32_t n, void *stream, sdugk
  * then return SDUGKS_EINVAL until a later sdugks_batch_set_members succeeds.
  * The same holds for the table refresh inside sdugks_batch_step. */
 int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_t n);
+/* Advance every member n >= 0 time steps (asynchronous on the batch stream),
+ * one launch per step and step form (structured or general, precision).
+ * Pairs of steps are replayed from hipGraphs of 2, 4, 8, 16 and 32 steps,
+ * all built at the first call that needs one (again after a membership
+ * change that rebuilds the launch): runs of 32, then one graph per set bit
+ * of the pairs left; an odd last step is launched alone.  SDUGKS_EDIVERGED
+ * when a member has been seen non-finite; SDUGKS_EINVAL for n < 0 or a
+ * failed batch. */
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n);
 
 /* Residual of every member (the definition of sdugks_residual, each against
