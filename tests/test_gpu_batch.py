@@ -54,7 +54,9 @@ def assert_same(a, b):
             assert np.array_equal(x, y)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 40])
+# step counts that replay every graph length: 30 = 8 + 4 + 2 + 1 pairs, 95 =
+# two 16-pair runs + 8 + 4 + 2 + 1 pairs + an odd step
+@pytest.mark.parametrize("n", [1, 2, 7, 30, 40, 95])
 def test_batch_equals_alone(sd, n):
     alone = make(sd, members(sd), seed=100)
     batched = make(sd, members(sd), seed=100)
