@@ -1,7 +1,7 @@
 """The structured step (tensor-product quad meshes, one lane per face) on the
 GPU: element-wise parity with the FP64 oracle from generic states on meshes
 covering every side condition, ragged tiles and periodic gluing in x, y or
-both; agreement with the general fused step; the batched form bitwise equal
+both, down to two cells along an axis; agreement with the general fused step; the batched form bitwise equal
 to stepping alone; the full-size 256 x 256 cavity."""
 import sys
 
@@ -64,6 +64,12 @@ CASES = {
     "half_channel_symmetry": (_half_channel, dict(nu=0.005, cfl=0.5)),
     "relabeled_cavity_17": (lambda: (meshgen.relabel(meshgen.cavity(17)[0], seed=2)[0], meshgen.cavity(17)[1]),
                             dict(nu=0.002, cfl=0.5)),
+    # the smallest structured meshes: two cells along an axis, every cell on
+    # two walls; two periodic columns (each cell's left and right neighbour
+    # the same cell, the halo wrapped across both sides); both axes periodic
+    "cavity_2": (lambda: meshgen.cavity(2), dict(nu=1e-3, cfl=0.5)),
+    "couette_2x3": (lambda: meshgen.couette(2, 3), dict(nu=0.01, cfl=0.5)),
+    "periodic_box_2x2": (lambda: meshgen.periodic_box(2, 2), dict(nu=0.004, cfl=0.5)),
 }
 
 
@@ -113,8 +119,8 @@ def test_window_against_oracle(sd, oracle_mod, name, scheme, macro):
 
 
 @pytest.mark.parametrize("prec", ["fp32dev", "fp32neq"])
-@pytest.mark.parametrize("name", ["cavity_23", "cavity_33", "cavity_40x40_lid", "couette_4x32", "periodic_box_18x9",
-                                  "periodic_box_40x30", "inlet_outlet_13x9"])
+@pytest.mark.parametrize("name", ["cavity_2", "cavity_23", "cavity_33", "cavity_40x40_lid", "couette_2x3", "couette_4x32",
+                                  "periodic_box_2x2", "periodic_box_18x9", "periodic_box_40x30", "inlet_outlet_13x9"])
 def test_fp32_window_against_oracle(sd, oracle_mod, name, prec):
     """The FP32 storage forms on the structured step, 40 steps from a generic
     state, with the bars of the general step's FP32 windows (f and rho
