@@ -253,9 +253,11 @@ def batch_headline(sdugks, autotune, meshgen, a, seed=2026, n_inst=64):
         sched, table = {"tile_cells": t, "block_threads": bt, "structured": 1}, []
     else:
         sched, table = autotune.autotune_batch(problems)
-    solvers = [sdugks.Solver(mesh, bcs, **sched, **kw) for mesh, bcs, kw in problems]
-    ws = sum(s.workspace.numel() for s in solvers)
+    # the members live on the batch's stream, as in a serving process with one
+    # stream for its batch: the batch then has no member streams to order after
     stream = torch.cuda.Stream()
+    solvers = [sdugks.Solver(mesh, bcs, stream=stream, **sched, **kw) for mesh, bcs, kw in problems]
+    ws = sum(s.workspace.numel() for s in solvers)
     b = sdugks.Batch(solvers, stream=stream)
     # the warm-up captures the batch's graphs (2 to 32 steps, all at the first call) and
     # replays the longest and the shortest, then the odd step
