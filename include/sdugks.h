@@ -27,6 +27,14 @@
  *    (NULL = the null stream).  sdugks_step is asynchronous; calls that return
  *    host data synchronise that stream first.
  *  - Threads: one handle must not be used by two threads at once.
+ *  - Step forms: the fused step (one kernel per time step over tiles of at
+ *    most 64 cells of triangles and quads) and, on tensor-product quad meshes,
+ *    the structured step run every precision form, both schemes and the
+ *    batched calls.  Meshes with polygons of more than four faces (or more
+ *    than 64 boundary-condition entries, or tile_cells = -1) take the
+ *    two-kernel step instead, which is limited: FP64 only, the simplified
+ *    scheme only, no batching (SDUGKS_EINVAL otherwise), and it writes fbar+
+ *    and its gradient to device memory, 432 B per cell per step more.
  */
 #ifndef SDUGKS_H
 #define SDUGKS_H
