@@ -802,9 +802,9 @@ def main():
             "traffic": measured_traffic("batch64_fp32dev" + ("" if structured else "_general"), hb["sched"]),
             "alg_bytes_per_cell": ALG_BYTES["fp32dev"], "cells_per_launch": cells, "kernel_ms": round(k_ms, 5),
             "working_set_MB": hb["working_set_MB"],
-            "note": "working set above the 256 MB Infinity Cache; achieved = algorithmic bytes per cell (the "
-                    "survey's 304 B: state plus stored geometry of a quad) x cells per launch / average launch "
-                    "duration (HIP events on the batch stream)"}
+            "note": "working set above the 256 MB Infinity Cache; achieved = algorithmic bytes per cell (304 B: "
+                    "the FP32 state read and written once plus the stored geometry of a general quad mesh) x cells "
+                    "per launch / average launch duration (HIP events on the batch stream)"}
     if structured:
         roof["kernel_own_bytes_per_cell"] = own
         roof["frac_of_own_bytes"] = round(own * cells / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
