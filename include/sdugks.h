@@ -273,8 +273,9 @@ int sdugks_batch_set_members(sdugks_batch_t *b, sdugks_t *const *members, int32_
  * one launch per step and step form (structured or general, precision).
  * Pairs of steps are replayed from hipGraphs of 2, 4, 8, 16 and 32 steps,
  * all built at the first call that needs one (again after a membership
- * change that rebuilds the launch): runs of 32, then one graph per set bit
- * of the pairs left; an odd last step is launched alone.  SDUGKS_EDIVERGED
+ * change that rebuilds the launch): one graph per set bit of the pairs
+ * left over after whole runs of 32 steps, the shortest first, then the runs;
+ * an odd last step is launched alone.  SDUGKS_EDIVERGED
  * when a member has been seen non-finite; SDUGKS_EINVAL for n < 0 or a
  * failed batch. */
 int sdugks_batch_step(sdugks_batch_t *b, int64_t n);

@@ -1202,17 +1202,19 @@ int sdugks_batch_step(sdugks_batch_t *b, int64_t n)
     if (rc) return rc;
     // whole runs of kGraphPairs pairs replay the longest graph, the remaining
     // pairs one graph per set bit (the runtime leaves a gap of several us
-    // between two graph launches, so few launches matter for short calls);
-    // all lengths are captured together at the first call that needs one
+    // between two graph launches, so few launches matter for short calls),
+    // the shortest first so that the device starts while the host submits
+    // the longer ones; all lengths are captured together at the first call
+    // that needs one
     int64_t pairs = n / 2;
     const int64_t runs = pairs / kGraphPairs;
     pairs -= runs * kGraphPairs;
     if (runs > 0 || pairs > 0)
         for (int k = 0; k < kBatchGraphs; k++)
             if (!b->exec[k] && (rc = batch_capture(b, (int64_t)1 << k, b->graph[k], b->exec[k]))) return rc;
-    for (int64_t k = 0; k < runs; k++) HIPCHK(hipGraphLaunch(b->exec[kBatchGraphs - 1], b->stream));
-    for (int k = kBatchGraphs - 2; k >= 0; k--)
+    for (int k = 0; k <= kBatchGraphs - 2; k++)
         if (pairs & ((int64_t)1 << k)) HIPCHK(hipGraphLaunch(b->exec[k], b->stream));
+    for (int64_t k = 0; k < runs; k++) HIPCHK(hipGraphLaunch(b->exec[kBatchGraphs - 1], b->stream));
     if (n & 1) {
         rc = batch_launch(b, 0);
         if (rc) return rc;
