@@ -750,7 +750,8 @@ def cavity256_form(sdugks, autotune, meshgen, a):
                       "steps": steps, "schedule": sched, "alg_bytes_per_cell": ab,
                       "effective_GBs": round(ab * nc / (k_ms / 1e3) / 1e9, 1),
                       "kernel_ms_event_per_launch": round(max(kt.values()), 5),
-                      "traffic_bytes_per_launch": measured_traffic(f"cavity256_{pname}", sched),
+                      "traffic_bytes_per_launch": measured_traffic(
+                          f"cavity256_{pname}" + ("_structured" if sched.get("structured") == 2 else ""), sched),
                       "working_set_MB": round(sdugks.state_bytes(mesh, bcs, **kw, **sched) / 1e6, 1)}
         s.close()
         progress(f"cavity 256 {pname}: {out[pname]['mlups']} MLUPS")
