@@ -69,10 +69,12 @@ enum { SDUGKS_BC_WALL = 1, SDUGKS_BC_INLET = 2, SDUGKS_BC_OUTLET = 3, SDUGKS_BC_
 
 /* Precision of f.  FP64: stored and computed in FP64.  FP32DEV: stored in
  * FP32 as the deviation f - w_i rho0 and advected in FP32 (fbar+, gradients,
- * face values and fluxes; compensated per-cell flux sums), with density,
+ * face values and fluxes; per-cell flux sums compensated in the general
+ * step, in FP64 in the structured step), with density,
  * momentum, their update, the macroscopic flux, mass and residual in FP64;
- * the rounding of its face arithmetic keeps the velocity residual from
- * falling below a few 1e-8 on fine meshes.  FP32NEQ: the non-equilibrium
+ * the rounding of its FP32 arithmetic (fbar+, gradients and face pass
+ * alike) keeps the velocity residual from falling below a few 1e-8 on fine
+ * meshes.  FP32NEQ: the non-equilibrium
  * part f - feq(rho, u) stored in FP32 (half the bytes of FP64 f), every
  * operation of the step in FP64; converges like FP64. */
 enum { SDUGKS_FP64 = 0, SDUGKS_FP32DEV = 1, SDUGKS_FP32NEQ = 2 };

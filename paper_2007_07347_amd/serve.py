@@ -23,7 +23,7 @@ An instance whose residual has stopped falling while still above the
 tolerance (no 20 % gain over `stall_checks` checks) is handed to the
 backend's optional escalate(): the GPU backend continues it from its current
 state with the same FP32 storage and FP64 arithmetic (FP32NEQ), which has
-no such floor (the floor comes from the FP32 face arithmetic), when the new
+no such floor (the floor comes from the FP32 arithmetic), when the new
 instance fits the remaining budget.
 
 A request whose instance cannot be made (the library rejects its mesh or
