@@ -26,9 +26,10 @@ state with the same FP32 storage and FP64 arithmetic (FP32NEQ), which has
 no such floor (the floor comes from the FP32 arithmetic), when the new
 instance fits the remaining budget.
 
-A request whose instance cannot be made (the library rejects its mesh or
-parameters, or the memory runs out) is retired as "failed" with the error's
-text, and its bytes return to the budget; the others are served as before.
+A request whose instance cannot be sized or made (the library rejects its
+mesh or parameters, or the memory runs out) is retired as "failed" with the
+error's text, and any bytes it held return to the budget; the others are
+served as before.
 A failed escalation leaves the request in its first form.
 
 Time-to-steady of a request = completion time - arrival time (queueing
@@ -133,7 +134,12 @@ class Server:
             # admission, FIFO: the head waits until it fits (no overtaking)
             while queue and len(active) + len(staging) < self.max_slots:
                 req = queue[0]
-                need = self.backend.bytes(req)
+                try:
+                    need = self.backend.bytes(req)
+                except Exception as e:          # the library refuses its mesh or parameters
+                    queue.pop(0)
+                    self._fail(results, req, now(), e)
+                    continue
                 if need > self.budget:
                     queue.pop(0)
                     results[req.rid] = Result(req.rid, req.kind, req.n_cells, "rejected", req.arrival, now(),
@@ -299,7 +305,11 @@ class SequentialServer(Server):
         for req in pending:
             if req.arrival > now():
                 self.sleep(req.arrival - now())
-            need = self.backend.bytes(req)
+            try:
+                need = self.backend.bytes(req)
+            except Exception as e:
+                self._fail(results, req, now(), e)
+                continue
             if need > self.budget:
                 results[req.rid] = Result(req.rid, req.kind, req.n_cells, "rejected", req.arrival, now(), now(), 0,
                                           math.inf)

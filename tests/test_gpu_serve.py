@@ -65,3 +65,32 @@ def test_stalled_request_continues_with_fp64_arithmetic():
     print("velocity L2 against FP64 alone", l2, flush=True)
     assert l2 <= 1e-5
     ref.close()
+
+
+def test_rejected_parameters_fail_alone():
+    """Requests the library refuses (no viscosity; the structured step asked
+    for on a triangle mesh) end as "failed" with the library's message, and
+    the valid requests of the same trace are served bit for bit as alone."""
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2007_07347_amd import sdugks, serve
+    good = [(meshgen.cavity(12), dict(nu=1e-3, cfl=0.5)), (meshgen.couette(4, 8), dict(nu=0.01, cfl=0.5))]
+    bad = [(meshgen.cavity(12), dict(nu=-1.0, cfl=0.5)),
+           (meshgen.cylinder_ogrid(24, 8, seed=1), dict(nu=2.5e-3, cfl=0.5, u0=0.1, structured=2))]
+    specs = [good[0], bad[0], good[1], bad[1]]
+    rq = [serve.Request(k, 0.0, m, b, p, "test", len(m["cell_ptr"]) - 1) for k, ((m, b), p) in enumerate(specs)]
+    srv = serve.Server(serve.GpuBackend(), budget_bytes=1 << 30, interval=500, tol=1e-7, step_cap=2000,
+                       keep_macros=True, stall_checks=0)
+    res, stats = srv.run(rq)
+    print([(r.status, r.error) for r in res], flush=True)
+    assert [r.status != "failed" for r in res] == [True, False, True, False]
+    assert "nu" in res[1].error and "structured" in res[3].error
+    for r, q in zip(res, rq):
+        if r.status == "failed":
+            continue
+        s = sdugks.Solver(q.mesh, q.bcs, precision=sdugks.FP32DEV, **q.params)
+        for _ in range(r.steps // 500):
+            s.step(500)
+        for a, b in zip(r.macros, s.macros()):
+            assert np.array_equal(a, b)
+        s.close()

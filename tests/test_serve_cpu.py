@@ -378,6 +378,13 @@ class FailingBackend(AsyncBackend):
         if not use_async:
             self.create_async = None
 
+    def bytes(self, req):
+        if req.params.get("unsized"):
+            e = ValueError(f"parameters of request {req.rid} rejected")
+            e.code = -1
+            raise e
+        return super().bytes(req)
+
     def create(self, req):
         if req.params.get("bad"):
             e = ValueError(f"mesh of request {req.rid} rejected")
@@ -413,12 +420,12 @@ def test_failed_creation_isolated_and_budget_returned(use_async):
         be.create_async = create_async
     # the budget holds one request at a time: the failed one must give its bytes back
     specs = [(0.0, 10, {"need": 2000, "bad": True}), (0.0, 10, {"need": 2000}), (0.0, 10, {"need": 1000, "bad": True}),
-             (0.0, 10, {"need": 1000})]
+             (0.0, 10, {"need": 1000}), (0.0, 10, {"need": 1000, "unsized": True}), (0.0, 10, {"need": 1000})]
     srv = Server(be, budget_bytes=1000, clock=clock, sleep=clock.sleep, interval=1000)
     res, stats = srv.run(reqs(specs))
-    assert [r.status for r in res] == ["failed", "converged", "failed", "converged"]
-    assert "rejected" in res[0].error and res[1].error == ""
-    assert stats["failed"] == 2 and stats["converged"] == 2
+    assert [r.status for r in res] == ["failed", "converged", "failed", "converged", "failed", "converged"]
+    assert "rejected" in res[0].error and res[1].error == "" and "parameters" in res[4].error
+    assert stats["failed"] == 3 and stats["converged"] == 3
     assert all(inst.closed for inst in be.live.values())
 
 
@@ -426,8 +433,9 @@ def test_failed_creation_in_the_sequential_loop():
     clock = SimClock()
     be = FailingBackend(clock, use_async=False)
     srv = SequentialServer(be, budget_bytes=10**6, clock=clock, sleep=clock.sleep, interval=1000)
-    res, stats = srv.run(reqs([(0.0, 10, {"need": 1000, "bad": True}), (0.0, 10, {"need": 1000})]))
-    assert [r.status for r in res] == ["failed", "converged"]
+    res, stats = srv.run(reqs([(0.0, 10, {"need": 1000, "bad": True}), (0.0, 10, {"need": 1000}),
+                               (0.0, 10, {"need": 1000, "unsized": True})]))
+    assert [r.status for r in res] == ["failed", "converged", "failed"]
 
 
 def test_failed_escalation_keeps_the_first_form():
