@@ -28,7 +28,12 @@ STRUCTURED = {"structured": 2}
 
 
 def label(sched):
-    return "structured" if sched.get("structured") == 2 else f"{sched['tile_cells']}/{sched['block_threads']}"
+    """Name of a schedule in timing tables: the lanes-per-face axis (one lane
+    per face on the structured step, four lanes per cell, one per face slot,
+    on the general step) and the general step's tile cells / threads."""
+    if sched.get("structured") == 2:
+        return "structured, 1 lane per face"
+    return f"general {sched['tile_cells']}/{sched['block_threads']}, 4 lanes per cell"
 
 
 def candidates_for(problems, candidates=None):
